@@ -1,0 +1,149 @@
+"""Benchmark: Hessenberg -> real Schur form (multishift QR + AED) on one MI355X.
+
+One step = one full hqr_schur call (T and Q) on the benchmark matrix, with the
+input already resident in HBM.  The default workload is the n = 4096 Gaussian
+Hessenberg matrix (upper triangle and subdiagonal i.i.d. N(0,1), seed 2020)
+with 64 shifts per sweep and an AED window of 256, Q accumulated from I.
+Prints one JSON line (see the design doc for the fields).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "gaussian_hessenberg_n4096": dict(n=4096, gen="gaussian", ns=64, nw=256),
+    "prescribed_hessenberg_n256": dict(n=256, gen="prescribed", ns=0, nw=0),
+    "prescribed_hessenberg_n16384": dict(n=16384, gen="prescribed", ns=256, nw=1024),
+    "hessrand_n4096": dict(n=4096, gen="hessrand", ns=64, nw=256),
+}
+
+
+def make_input(spec, seed):
+    import hqr_inputs as hi
+    n = spec["n"]
+    if spec["gen"] == "gaussian":
+        return hi.gaussian_hessenberg(n, seed=seed)
+    if spec["gen"] == "hessrand":
+        return hi.hessrand(n, seed=seed)
+    H, _ = hi.prescribed_hessenberg(n, seed=seed)
+    return H
+
+
+def cpu_baseline(spec, seed, target_n):
+    """The oracle on a bounded sample of the same workload (same generator
+    and parameters, order target_n), single thread; returns nominal TFLOP/s."""
+    import oracle
+    import hqr_inputs as hi
+    if spec["gen"] == "gaussian":
+        H = hi.gaussian_hessenberg(target_n, seed=seed)
+    elif spec["gen"] == "hessrand":
+        H = hi.hessrand(target_n, seed=seed)
+    else:
+        H, _ = hi.prescribed_hessenberg(target_n, seed=seed)
+    t0 = time.perf_counter()
+    T, Q, w, info, st = oracle.schur(H, want_q=True, ns=spec["ns"], nw=spec["nw"])
+    dt = time.perf_counter() - t0
+    assert info == 0
+    return {"value": 10.0 * target_n ** 3 / dt / 1e12, "unit": "TFLOP/s (10n^3 nominal)", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one full solve of the same workload at n={target_n} (same generator, ns={spec['ns']}, "
+                      f"nw={spec['nw']}, Q accumulated): {dt:.2f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="gaussian_hessenberg_n4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=2020)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=2048)
+    ap.add_argument("--streams", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2007_03576_amd as hq
+    from paper_2007_03576_amd import profiling
+
+    spec = WORKLOADS[args.workload]
+    n = spec["n"]
+    dev = torch.device("cuda:0")
+    H0 = make_input(spec, args.seed)
+    H0d = torch.from_numpy(np.ascontiguousarray(H0.T)).to(dev)  # row-major of H^T = column-major H
+    params = {"ns": spec["ns"], "nw": spec["nw"], "streams": args.streams}
+    nsteps = args.warmup + args.steps
+    # stage one input copy per step so the timed region is solves only
+    Hs = [H0d.clone() for _ in range(nsteps)]
+    eye = torch.eye(n, dtype=torch.float64, device=dev)
+    Qs = [eye.clone() for _ in range(nsteps)]
+    wr = torch.empty(n, dtype=torch.float64, device=dev)
+    wi = torch.empty_like(wr)
+
+    def view(x):  # column-major view of the staged buffer
+        return x.t()
+
+    infos = []
+    for i in range(args.warmup):
+        infos.append(hq.schur_colmajor(view(Hs[i]), view(Qs[i]), wr, wi, params=params))
+    torch.cuda.synchronize()
+    profiling.enable(True)
+    profiling.reset()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, nsteps):
+        infos.append(hq.schur_colmajor(view(Hs[i]), view(Qs[i]), wr, wi, params=params))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = profiling.read()
+    profiling.enable(False)
+    stats = hq.last_stats()
+    dt = (t1 - t0) / args.steps
+    assert all(i == 0 for i in infos), infos
+    # accuracy of the last solve (host check, outside the timed region)
+    T = Hs[-1].t().cpu().numpy()
+    Q = Qs[-1].t().cpu().numpy()
+    u = 2.0 ** -52
+    be = float(np.linalg.norm(Q.T @ H0 @ Q - T) / np.linalg.norm(H0))
+    orth = float(np.linalg.norm(Q.T @ Q - np.eye(n)))
+    nominal = 10.0 * n ** 3
+    out = {
+        "metric": "FP64 TFLOP/s (10n^3 nominal) & Schur solves/sec, batched+grad vs plain, 1 MI355X",
+        "value": nominal / dt / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "ns": spec["ns"], "nw": spec["nw"],
+                   "want_q": True, "seed": args.seed},
+        "solves_per_s": 1.0 / dt,
+        "accuracy": {"backward_rel": be, "backward_u": be / u, "orth": orth, "bound_100nu": 100 * n * u},
+        "run_stats": stats,
+    }
+    out["roofline"] = profiling.roofline(prof, args.steps)
+    out["kernel_times"] = profiling.summary(prof, args.steps)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, args.seed, args.cpu_n)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,120 @@
+/*
+ * hqr.h -- C-ABI of libhqr.so: Hessenberg -> real Schur form on one MI355X (gfx950).
+ *
+ * The operation is the multishift QR algorithm with aggressive early deflation
+ * (AED) of Myllykoski, "Algorithm 1019: A Task-based Multi-shift QR/QZ Algorithm
+ * with Aggressive Early Deflation", ACM TOMS 48(1), 2021:
+ *   - problem statement: Sec. 2, eqs. (hessenberg_form), (schur_form), (2by2_blocks):
+ *     H = Q T Q^T with T upper quasi-triangular, 1x1 blocks for real eigenvalues
+ *     and 2x2 blocks for complex conjugate pairs;
+ *   - the iteration H <- Qhat^T H Qhat, Q <- Q Qhat: Sec. 2.1;
+ *   - tightly coupled bulge chains chased in diagonal windows whose accumulated
+ *     transformations are applied off-diagonal by matrix products: Sec. 2.3;
+ *   - AED (window Schur form, spike test with eigenvalue reordering, Hessenberg
+ *     restoration): Sec. 2.5; deflation conditions: Sec. 5.3 (LAPACK-style).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are FP64, column major.  All matrix/vector pointers are DEVICE
+ *     pointers unless stated otherwise; the caller owns every buffer.
+ *   - Return value: 0 ok; -k argument k invalid (non-finite H entries count as
+ *     argument 1); +i failed to converge within the iteration limit (the
+ *     1-based rows i+1..n hold converged eigenvalues); -1000-e a HIP runtime
+ *     error e.
+ *   - Streams: work is ordered after prior work on `stream` (0 = the legacy
+ *     default stream).  The library keeps per-device workspace and helper
+ *     streams, created on first use and released by hqr_finalize().
+ */
+#ifndef HQR_H
+#define HQR_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Algorithm parameters; a zero field means "automatic".
+ *   ns      shifts per sweep (even)                         (Sec. 2.3)
+ *   nw      AED window size                                  (Sec. 2.5)
+ *   nmin    blocks of order <= nmin go to the small solver   (task 'small Schur', Sec. 3.1)
+ *   nibble  skip the sweep when 100*nd > nibble*nw           (Sec. 2.5, repeated AED)
+ *   kexsh   exceptional shifts after kexsh steps without deflation
+ *   itmax   iteration limit (AED steps + sweeps)             (Sec. 2.1)
+ *   window  bulge-chasing window order (<= 96)              (Sec. 3.1, 'push bulges')
+ *   bulges_per_window  bulges in one window chain
+ *   defl_mode  0 = LAPACK-style conditions (the only mode implemented)
+ *   streams    1 = everything on the caller's stream; 2 = updates outside the
+ *              active block and to Q on a second stream (Sec. 3.3 priorities) */
+typedef struct hqr_params {
+    int ns, nw, nmin, nibble, kexsh;
+    int64_t itmax;
+    int window, bulges_per_window;
+    int defl_mode;
+    double defl_thold;
+    int streams;
+} hqr_params;
+
+/* Process-wide defaults used by later calls.  Returns 0 or -1 (NULL / invalid). */
+int hqr_set_params(const hqr_params *p);
+/* Current defaults (zeros mean automatic). */
+int hqr_get_params(hqr_params *p);
+
+/* Reduce the upper Hessenberg H (n x n, leading dimension ld >= max(1,n)) to
+ * real Schur form.  In: H upper Hessenberg (entries below the first
+ * subdiagonal are ignored); Q = Q0 (identity or a Hessenberg-reduction
+ * factor), or NULL to skip accumulation (Q then uses the same ld).
+ * Out: H = T (standardized 2x2 blocks, exact zeros below the subdiagonal;
+ * padding rows n..ld-1 untouched), Q = Q0 * Qhat, wr/wi (device, n entries)
+ * = eigenvalues in diagonal order, conjugate pairs adjacent with wi > 0 first.
+ * Blocks the host until done: the driver reads back one small status record
+ * per iteration (the deflation count and the shifts of each AED step). */
+int hqr_schur(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi, void *stream);
+
+/* Same as hqr_schur with explicit parameters for this call only (p may be NULL). */
+int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi, void *stream,
+                 const hqr_params *p);
+
+/* Batched form for many small independent problems (one persistent launch,
+ * one workgroup per matrix).  Matrix i has order n[i] <= 96, stored packed
+ * column major at H + offsets[i] with leading dimension n[i]; Q likewise
+ * (Q may be NULL; otherwise it must hold Q0, e.g. identity, on entry).
+ * Eigenvalues of matrix i go to wr/wi + eig_offsets[i]; info[i] receives the
+ * per-matrix code (0 or +i).  offsets, n, eig_offsets, info are device
+ * arrays.  Fully asynchronous on `stream`; allocates nothing on the device. */
+int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int32_t batch,
+                      double *wr, double *wi, const int64_t *eig_offsets, int32_t *info, void *stream);
+
+/* Backward pass of the eigenvalues for a batch of Schur forms (T_i, Q_i) of
+ * equal order n <= 96 stored back to back (T + i*n*n).  Given the cotangents
+ * g = dL/dRe(lambda) + i dL/dIm(lambda) (gwr/gwi, n per matrix, ordered as
+ * wr/wi), writes dH_i = Re(conj(Y) diag(conj(g)/(y^H x)) X^T) where X, Y hold
+ * the right and left eigenvectors (Sec. 2 eigenvector relation x = Q y);
+ * hess_mask != 0 zeroes entries below the first subdiagonal.  Asynchronous. */
+int hqr_eig_backward_batched(const double *T, const double *Q, int32_t n, int32_t batch,
+                             const double *wr, const double *wi, const double *gwr, const double *gwi,
+                             double *dH, int32_t hess_mask, void *stream);
+
+/* Timing and counters of the last hqr_schur call on this thread:
+ * stats[0] AED steps, [1] sweeps, [2] shifts used, [3] eigenvalues deflated by
+ * AED, [4] small-solver calls, [5] host synchronizations, [6] kernel launches,
+ * [7] chase windows.  Returns the number of entries written (<= len). */
+int hqr_last_stats(int64_t *stats, int len);
+
+/* Kernel-class timing for measurement tools.  When enabled, the driver
+ * brackets its launches with HIP events on the launching stream and sums the
+ * elapsed times per class: 0 one-workgroup LDS iteration (small solver / AED),
+ * 1 bulge-chasing windows, 2 FP64-MFMA update products, 3 large-window AED
+ * kernels, 4 other.  hqr_profile_read returns, per class, milliseconds,
+ * launches, and the algorithmic flops and bytes the driver counted for those
+ * launches (update products: 2 K^2 per panel row/column; bytes: panel read
+ * and write plus the factor).  Reading synchronizes with the recorded events.
+ * Returns the number of classes written, or -1 on NULL arguments. */
+int hqr_profile_enable(int on);
+int hqr_profile_reset(void);
+int hqr_profile_read(double *ms, int64_t *launches, double *flops, double *bytes, int nclass);
+
+/* Free per-device workspace and helper streams. */
+int hqr_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

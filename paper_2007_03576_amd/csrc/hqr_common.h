@@ -1,0 +1,123 @@
+// Internal declarations shared by the kernels and the host driver of libhqr.
+// Not part of the public ABI (see include/hqr.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hqr {
+
+// Largest matrix order the one-workgroup solver keeps in LDS together with its
+// accumulated orthogonal factor (2 * 96 * 97 * 8 B = 149 KB of the 160 KB LDS).
+constexpr int MMAX = 96;
+constexpr int LDM = MMAX + 1;      // odd leading dimension: spreads LDS banks
+constexpr int NT = 256;            // threads of the LDS kernels (4 waves)
+constexpr int WMAX = 96;           // largest bulge-chasing window
+constexpr int GMAX = 16;           // most bulges chased in one window
+constexpr int MAXWIN = 16;         // most windows in one chase round
+constexpr int MAXCAND = 1024;      // candidate eigenvalues returned by one AED step
+
+// Status record of one iteration, written by the device and read back by the
+// host (the only host synchronization per iteration).
+struct IterStatus {
+    int kind;    // 0: the block was small and is now in Schur form; 1: AED step
+    int ktop;    // top row of the active block
+    int kwtop;   // top row of the AED window (kind 1) / of the block (kind 0)
+    int nw;      // order of the window / block that was transformed
+    int nd;      // eigenvalues deflated (kind 1)
+    int ns;      // undeflated candidates (kind 1)
+    int ncand;   // number of candidate eigenvalues in cr/ci
+    int info;    // 0, or >0 when the small solver did not converge
+    int changed; // 1 when H was modified and the factor must be propagated
+    int pad;
+    double beta; // new subdiagonal entry left of an AED window after restoration
+    double cr[MAXCAND];
+    double ci[MAXCAND];
+};
+
+// One bulge-chasing window of a chase round.  Global row/column indices.
+struct ChaseWin {
+    int a, wa;        // window rows/cols a .. a+wa-1
+    int p0;           // position of the group's lowest bulge at step 0
+    int nsteps;       // chase steps in this window
+    int kend;         // last reflector position allowed in this window
+    int nb;           // bulges of the group
+    int shift_off;    // index of the group's first shift in the shift array
+    int slot;         // index of the U buffer written by this window
+    int vig_lo, vig_hi; // positions whose subdiagonal is final after the top bulge passes
+};
+
+struct ChaseRound {
+    int nwin;
+    int ktop, kbot;
+    ChaseWin w[MAXWIN];
+};
+
+// One in-place update X <- X*U (side 0) or X <- U^T*X (side 1) with U of order
+// K (stored transposed, padded to K16 = round_up(K,16): Ut[j + k*K16] = U[k][j]).
+//   side 0: X is a (rows x K) panel: element (r, k) at X[r + k*ldx]
+//   side 1: X is a (K x cols) panel: element (k, c) at X[k + c*ldx]
+struct UpdJob {
+    double *X;
+    const double *Ut;
+    int64_t ldx;
+    int count;   // rows (side 0) or columns (side 1) of the panel
+    int K, K16;
+    int side;
+    int tile;    // panel rows/cols per workgroup
+    int tiles;   // ceil(count / tile)
+    int pad;
+};
+constexpr int MAXJOBS = 48;
+struct UpdBatch {
+    int njobs;
+    int pad;
+    int first_tile[MAXJOBS + 1];
+    UpdJob job[MAXJOBS];
+};
+
+// ---- launchers (hqr_lds.hip) ----
+// One driver iteration on the active block that ends at kbot: locate ktop,
+// then either reduce a small block to Schur form or perform an AED step with
+// window nw (<= MMAX).  Writes the factor (transposed, padded) to Ut.
+hipError_t launch_iter(double *H, int64_t ld, int n, int ilo, int kbot, int nw, int nmin,
+                       double smlnum, int64_t itmax, double *Ut, IterStatus *st, hipStream_t s);
+// Locate the top of the active block only (st->ktop).
+hipError_t launch_find_block(double *H, int64_t ld, int ilo, int kbot, double smlnum, IterStatus *st,
+                             hipStream_t s);
+// Chase round: one workgroup per window; U factors written transposed to Ubuf.
+hipError_t launch_chase(double *H, int64_t ld, const ChaseRound &r, const double *sr, const double *si,
+                        double smlnum, double *Ubuf, int64_t ustride, hipStream_t s);
+// Deflation check of the bottom corner of a large AED window (T in global
+// memory, order nw; the corner has order wd <= MMAX) with reordering.
+hipError_t launch_corner_deflate(double *T, int64_t ldt, int nw, int wd, const double *V, int64_t ldv,
+                                 double s, double smlnum, double *Ut, IterStatus *st, hipStream_t stream);
+// Hessenberg restoration of T(0:ns,0:ns) in global memory with the spike,
+// applied to T(0:ns, ns:nw) and to V (rows 0..nv-1).
+hipError_t launch_restore(double *T, int64_t ldt, int nw, int ns, double *V, int64_t ldv, int nv,
+                          double s, double *work, IterStatus *st, hipStream_t stream);
+// Copy a window out of H (zeroing below the subdiagonal), set V = I.
+hipError_t launch_window_copy(const double *H, int64_t ld, int kwtop, int nw, double *T, int64_t ldt,
+                              double *V, int64_t ldv, hipStream_t s);
+// Eigenvalues of the diagonal blocks of a quasi-triangular T(0:m, 0:m).
+hipError_t launch_block_eigs(const double *T, int64_t ldt, int m, double *wr, double *wi,
+                             hipStream_t s);
+// Standardize all 2x2 blocks of T (n x n) and extract eigenvalues, applying
+// the rotations to T and Q (may be NULL).
+hipError_t launch_finalize_ws(double *H, int64_t ld, int n, double *Q, double *wr, double *wi, double *ws,
+                              hipStream_t s);
+hipError_t launch_check_finite(const double *H, int64_t ld, int n, int *flag, hipStream_t s);
+hipError_t launch_zero_lower(double *H, int64_t ld, int n, hipStream_t s);
+hipError_t launch_transpose_pad(const double *V, int64_t ldv, int K, double *Ut, int K16,
+                                hipStream_t s);
+hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch,
+                          double *wr, double *wi, const int64_t *eoff, int32_t *info, double *logbuf,
+                          hipStream_t s);
+hipError_t launch_eig_backward(const double *T, const double *Q, int n, int batch, const double *wr,
+                               const double *wi, const double *gwr, const double *gwi, double *dH,
+                               int hess_mask, hipStream_t s);
+
+// ---- launchers (hqr_gemm.hip) ----
+hipError_t launch_updates(const UpdBatch &b, hipStream_t s);
+int update_tile(int K16, int side);
+
+} // namespace hqr

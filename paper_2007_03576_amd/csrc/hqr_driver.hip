@@ -1,0 +1,994 @@
+// Host driver and C-ABI of libhqr: multishift QR with aggressive early
+// deflation on one GPU (Myllykoski, ACM TOMS 48(1), 2021).
+//
+// The driver is the single-GPU form of the paper's event-driven main loop
+// (Sec. 3.2): the bottom unreduced block of the active segment is either
+// handed to the small solver or gets an AED step; the AED outcome (number of
+// deflated eigenvalues and the shift candidates) is the one value the host
+// waits for in each iteration -- the analogue of acquiring the 'small AED'
+// return handle.  A repeated AED is chosen when many eigenvalues deflated
+// (Sec. 2.5); otherwise a multishift sweep is enqueued as rounds of
+// concurrent bulge-chasing windows ('push bulges') followed by the left and
+// right update products (Sec. 3.3).  Updates that cannot feed back into the
+// active block (columns right of it, rows above it, and Q) run on a second
+// stream at default priority, ordered after their inputs by events, so the
+// window chain and the AED -- the critical path of Sec. 3.3.1 -- never wait
+// for them.
+#include "hqr_common.h"
+#include "../../include/hqr.h"
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+using namespace hqr;
+
+namespace {
+
+std::mutex g_mu;
+hqr_params g_params = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0.0, 0};
+thread_local int64_t t_stats[8];
+
+struct Params {
+    int ns, nw, nmin, nibble, kexsh;
+    int64_t itmax;
+    int window, gsize;
+    int streams;
+};
+
+// Reading of automatic parameters: LAPACK's documented shift-count table and
+// an AED window of ns (order <= 500) or 3ns/2 above, capped where noted.
+void auto_ns_nw(int nh, int &ns, int &nw)
+{
+    int s;
+    if (nh < 30) s = 2;
+    else if (nh < 60) s = 4;
+    else if (nh < 150) s = 10;
+    else if (nh < 590) {
+        int lg = (int)std::lround(std::log2((double)nh));
+        s = std::max(10, nh / std::max(lg, 1));
+    } else if (nh < 3000) s = 64;
+    else if (nh < 6000) s = 128;
+    else s = 256;
+    s &= ~1;
+    ns = s;
+    nw = (nh <= 500) ? s : 3 * s / 2;
+}
+
+hipError_t g_err = hipSuccess;
+#define CK(x)                                                                                                 \
+    do {                                                                                                       \
+        hipError_t e_ = (x);                                                                                   \
+        if (e_ != hipSuccess) {                                                                                \
+            g_err = e_;                                                                                        \
+            return -1000 - (int)e_;                                                                            \
+        }                                                                                                      \
+    } while (0)
+
+struct Workspace {
+    int dev = -1;
+    hipStream_t lo = nullptr;          // deferred-update stream
+    IterStatus *st_dev = nullptr;
+    IterStatus *st_host = nullptr;     // pinned
+    double *sh_host = nullptr;         // pinned shifts staging
+    double *d_shift = nullptr;         // device shifts (re, im)
+    double *ubuf = nullptr;            // ring of window factors
+    int nslots = 0;
+    int slot_next = 0;
+    std::vector<hipEvent_t> slot_ev;   // recorded on lo after the slot's last use
+    std::vector<char> slot_used;
+    double *fin = nullptr;             // finalize scratch
+    size_t fin_n = 0;
+    std::vector<double *> wT, wV, wU;  // per recursion depth: AED window, its factor, factor^T
+    std::vector<int> wcap;
+    std::vector<hipEvent_t> wU_ev;     // recorded on lo after the last deferred use of wU
+    std::vector<char> wU_pending;
+    double *vbuf = nullptr;
+    int *flag = nullptr;
+    hipEvent_t ev_pool[64];
+    int ev_next = 0;
+    bool init = false;
+};
+
+Workspace g_ws[16];
+
+// ---- optional kernel-class timing with HIP events (measurement tools) ----
+constexpr int NCLASS = 5; // 0 LDS iteration, 1 chase windows, 2 update products, 3 large-AED kernels, 4 other
+struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+    double flops, bytes;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_prof_pool;
+double g_prof_ms[NCLASS], g_prof_flops[NCLASS], g_prof_bytes[NCLASS];
+int64_t g_prof_n[NCLASS];
+
+hipEvent_t prof_event()
+{
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+int prof_begin(int cls, hipStream_t s)
+{
+    if (!g_prof_on) return -1;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    ProfRec r;
+    r.cls = cls;
+    r.a = prof_event();
+    r.b = prof_event();
+    r.flops = r.bytes = 0.0;
+    hipEventRecord(r.a, s);
+    g_prof.push_back(r);
+    return (int)g_prof.size() - 1;
+}
+
+void prof_end(int id, hipStream_t s, double flops, double bytes)
+{
+    if (id < 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    hipEventRecord(g_prof[id].b, s);
+    g_prof[id].flops = flops;
+    g_prof[id].bytes = bytes;
+}
+
+// fold finished records into the per-class totals
+void prof_collect()
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &r : g_prof) {
+        hipEventSynchronize(r.b);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            g_prof_ms[r.cls] += ms;
+            g_prof_flops[r.cls] += r.flops;
+            g_prof_bytes[r.cls] += r.bytes;
+            g_prof_n[r.cls] += 1;
+        }
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_prof.clear();
+}
+
+int slot_ustride() { return WMAX * WMAX; }
+
+struct Ctx {
+    Workspace *W;
+    hipStream_t hi; // caller's stream: the critical path
+    bool two;       // deferred updates on W->lo
+    double smlnum;
+    Params P;
+    int64_t *stats;
+};
+
+int ensure_ws(Workspace &W, int dev)
+{
+    if (W.init) return 0;
+    W.dev = dev;
+    CK(hipStreamCreateWithFlags(&W.lo, hipStreamNonBlocking));
+    CK(hipMalloc(&W.st_dev, sizeof(IterStatus)));
+    CK(hipHostMalloc(&W.st_host, sizeof(IterStatus), hipHostMallocDefault));
+    CK(hipHostMalloc(&W.sh_host, sizeof(double) * 2 * 2048, hipHostMallocDefault));
+    CK(hipMalloc(&W.d_shift, sizeof(double) * 2 * 2048));
+    W.nslots = 512;
+    CK(hipMalloc(&W.ubuf, sizeof(double) * (size_t)slot_ustride() * W.nslots));
+    W.slot_ev.resize(W.nslots);
+    W.slot_used.assign(W.nslots, 0);
+    for (int i = 0; i < W.nslots; ++i) CK(hipEventCreateWithFlags(&W.slot_ev[i], hipEventDisableTiming));
+    for (int i = 0; i < 64; ++i) CK(hipEventCreateWithFlags(&W.ev_pool[i], hipEventDisableTiming));
+    CK(hipMalloc(&W.flag, sizeof(int) * 4));
+    W.init = true;
+    return 0;
+}
+
+hipEvent_t next_event(Workspace &W)
+{
+    hipEvent_t e = W.ev_pool[W.ev_next];
+    W.ev_next = (W.ev_next + 1) % 64;
+    return e;
+}
+
+// A slot of the factor ring; waits (on the critical stream) until the
+// deferred stream has finished with its previous contents.
+int take_slot(Ctx &C)
+{
+    Workspace &W = *C.W;
+    int s = W.slot_next;
+    W.slot_next = (W.slot_next + 1) % W.nslots;
+    if (C.two && W.slot_used[s]) {
+        hipStreamWaitEvent(C.hi, W.slot_ev[s], 0);
+    }
+    W.slot_used[s] = 1;
+    return s;
+}
+
+double *slot_ptr(Workspace &W, int s) { return W.ubuf + (size_t)s * slot_ustride(); }
+
+void release_slot(Ctx &C, int s)
+{
+    if (C.two) hipEventRecord(C.W->slot_ev[s], C.W->lo);
+}
+
+int ensure_depth(Workspace &W, int depth, int w)
+{
+    if ((int)W.wT.size() <= depth) {
+        W.wT.resize(depth + 1, nullptr);
+        W.wV.resize(depth + 1, nullptr);
+        W.wU.resize(depth + 1, nullptr);
+        W.wcap.resize(depth + 1, 0);
+        size_t old = W.wU_ev.size();
+        W.wU_ev.resize(depth + 1, nullptr);
+        W.wU_pending.resize(depth + 1, 0);
+        for (size_t d = old; d <= (size_t)depth; ++d) CK(hipEventCreateWithFlags(&W.wU_ev[d], hipEventDisableTiming));
+    }
+    if (W.wcap[depth] >= w) return 0;
+    if (W.wT[depth]) {
+        hipFree(W.wT[depth]);
+        hipFree(W.wV[depth]);
+        hipFree(W.wU[depth]);
+    }
+    int w16 = (w + 15) & ~15;
+    CK(hipMalloc(&W.wT[depth], sizeof(double) * (size_t)w * w));
+    CK(hipMalloc(&W.wV[depth], sizeof(double) * (size_t)w * w));
+    CK(hipMalloc(&W.wU[depth], sizeof(double) * (size_t)w16 * w16));
+    W.wcap[depth] = w;
+    if (!W.vbuf) CK(hipMalloc(&W.vbuf, sizeof(double) * 16384));
+    return 0;
+}
+
+// Matrix view: H (n x n, ld), Q (nq rows, ldq) -- transformations act on
+// H's full rows/columns and on Q's columns.
+struct View {
+    double *H;
+    int64_t ld;
+    int n;
+    double *Q;
+    int64_t ldq;
+    int nq;
+};
+
+void add_job(UpdBatch &b, double *X, int64_t ldx, int count, int K, const double *Ut, int side)
+{
+    if (count <= 0 || K <= 0) return;
+    int K16 = (K + 15) & ~15;
+    UpdJob &J = b.job[b.njobs];
+    J.X = X;
+    J.Ut = Ut;
+    J.ldx = ldx;
+    J.count = count;
+    J.K = K;
+    J.K16 = K16;
+    J.side = side;
+    J.tile = update_tile(K16, side);
+    J.tiles = (count + J.tile - 1) / J.tile;
+    b.first_tile[b.njobs + 1] = b.first_tile[b.njobs] + J.tiles;
+    b.njobs++;
+}
+
+int flush(UpdBatch &b, hipStream_t s, Ctx &C)
+{
+    if (b.njobs > 0) {
+        double fl = 0.0, by = 0.0;
+        for (int j = 0; j < b.njobs; ++j) {
+            double K = b.job[j].K, cnt = b.job[j].count;
+            fl += 2.0 * K * K * cnt;
+            by += 16.0 * K * cnt + 8.0 * K * K;
+        }
+        int pid = prof_begin(2, s);
+        CK(launch_updates(b, s));
+        prof_end(pid, s, fl, by);
+        if (C.stats) C.stats[6]++;
+    }
+    b.njobs = 0;
+    b.first_tile[0] = 0;
+    return 0;
+}
+
+UpdBatch make_batch()
+{
+    UpdBatch b;
+    b.njobs = 0;
+    b.first_tile[0] = 0;
+    return b;
+}
+
+// Apply the factor of a transformed diagonal block [kw, kw+m) of the active
+// block [ktop, kbot] to the rest of the view.  Parts inside the active block
+// run on the critical stream; the rest (and Q) on the deferred stream.
+int apply_factor(Ctx &C, const View &V, int ktop, int kbot, int kw, int m, const double *Ut)
+{
+    UpdBatch hiL = make_batch(), hiR = make_batch(), loL = make_batch(), loR = make_batch();
+    int c0 = kw + m; // first column right of the block
+    int ncol_in = std::max(0, std::min(kbot, V.n - 1) - c0 + 1);
+    int ncol_out = V.n - c0 - ncol_in;
+    int nrow_in = std::max(0, kw - ktop);
+    int nrow_out = kw - nrow_in;
+    if (!C.two) {
+        add_job(hiL, V.H + kw + (int64_t)c0 * V.ld, V.ld, V.n - c0, m, Ut, 1);
+        add_job(hiR, V.H + (int64_t)kw * V.ld, V.ld, kw, m, Ut, 0);
+        if (V.Q) add_job(hiR, V.Q + (int64_t)kw * V.ldq, V.ldq, V.nq, m, Ut, 0);
+        if (flush(hiL, C.hi, C)) return g_err ? -1000 - (int)g_err : -1;
+        if (flush(hiR, C.hi, C)) return -1;
+        return 0;
+    }
+    add_job(hiL, V.H + kw + (int64_t)c0 * V.ld, V.ld, ncol_in, m, Ut, 1);
+    add_job(hiR, V.H + ktop + (int64_t)kw * V.ld, V.ld, nrow_in, m, Ut, 0);
+    add_job(loL, V.H + kw + (int64_t)(c0 + ncol_in) * V.ld, V.ld, ncol_out, m, Ut, 1);
+    add_job(loR, V.H + (int64_t)kw * V.ld, V.ld, nrow_out, m, Ut, 0);
+    if (V.Q) add_job(loR, V.Q + (int64_t)kw * V.ldq, V.ldq, V.nq, m, Ut, 0);
+    // critical updates
+    if (flush(hiL, C.hi, C)) return -1;
+    if (flush(hiR, C.hi, C)) return -1;
+    // deferred updates: after the factor exists and after the critical
+    // updates (the deferred regions never overlap the active block, but the
+    // left/right products of one factor share no data, so only the factor
+    // itself orders them)
+    if (loL.njobs + loR.njobs > 0) {
+        hipEvent_t e = next_event(*C.W);
+        hipEventRecord(e, C.hi);
+        hipStreamWaitEvent(C.W->lo, e, 0);
+        if (flush(loL, C.W->lo, C)) return -1;
+        if (flush(loR, C.W->lo, C)) return -1;
+    }
+    return 0;
+}
+
+int read_status(Ctx &C, int ncand)
+{
+    Workspace &W = *C.W;
+    size_t head = offsetof(IterStatus, cr);
+    CK(hipMemcpyAsync(W.st_host, W.st_dev, head, hipMemcpyDeviceToHost, C.hi));
+    if (ncand > 0) {
+        ncand = std::min(ncand, MAXCAND);
+        CK(hipMemcpyAsync(W.st_host->cr, W.st_dev->cr, sizeof(double) * ncand, hipMemcpyDeviceToHost, C.hi));
+        CK(hipMemcpyAsync(W.st_host->ci, W.st_dev->ci, sizeof(double) * ncand, hipMemcpyDeviceToHost, C.hi));
+    }
+    CK(hipStreamSynchronize(C.hi));
+    if (C.stats) C.stats[5]++;
+    return 0;
+}
+
+// --------------------------------------------------------------------------
+// multishift sweep
+
+int sweep(Ctx &C, const View &V, int ktop, int kbot, int nsh, const double *sr, const double *si)
+{
+    Workspace &W = *C.W;
+    int nb = nsh / 2;
+    if (nb <= 0) return 0;
+    for (int i = 0; i < nsh; ++i) {
+        W.sh_host[i] = sr[i];
+        W.sh_host[2048 + i] = si[i];
+    }
+    CK(hipMemcpyAsync(W.d_shift, W.sh_host, sizeof(double) * nsh, hipMemcpyHostToDevice, C.hi));
+    CK(hipMemcpyAsync(W.d_shift + 2048, W.sh_host + 2048, sizeof(double) * nsh, hipMemcpyHostToDevice, C.hi));
+    int w = std::min(C.P.window, WMAX);
+    int g = std::min(nb, std::min(C.P.gsize, GMAX));
+    // the window must hold the group chain plus room to move
+    while (g > 1 && 3 * g + 2 > w - 8) --g;
+    int ngroups = (nb + g - 1) / g;
+    struct Grp {
+        int nb, p0, soff;
+        bool started, done;
+    };
+    std::vector<Grp> G(ngroups);
+    for (int i = 0; i < ngroups; ++i) {
+        G[i].nb = std::min(g, nb - i * g);
+        G[i].p0 = ktop - 1;
+        G[i].soff = 2 * i * g;
+        G[i].started = false;
+        G[i].done = false;
+    }
+    int remaining = ngroups;
+    int guard = 0;
+    while (remaining > 0) {
+        if (++guard > 100000) return -99;
+        ChaseRound R;
+        R.nwin = 0;
+        R.ktop = ktop;
+        R.kbot = kbot;
+        int lower_a = INT32_MAX; // top of the window of the next lower group this round
+        for (int gi = 0; gi < ngroups && R.nwin < MAXWIN; ++gi) {
+            Grp &gr = G[gi];
+            if (gr.done) continue;
+            int a;
+            if (!gr.started) {
+                a = ktop;
+            } else {
+                a = gr.p0 - 3 * (gr.nb - 1);
+            }
+            int wa = std::min(w, kbot - a + 1);
+            if (a + wa > lower_a) wa = lower_a - a;
+            bool final_w = (a + wa - 1 >= kbot);
+            int kend = final_w ? kbot - 2 : a + wa - 5;
+            int top_next = gr.p0 - 3 * (gr.nb - 1);
+            int nsteps;
+            if (final_w)
+                nsteps = (kbot - 2) - top_next + 1;
+            else
+                nsteps = kend - gr.p0 + 1;
+            bool ok = wa >= 4 && nsteps > 0 && (final_w || wa >= 3 * gr.nb + 2);
+            if (!ok) {
+                if (!gr.started) break; // later groups cannot start either
+                lower_a = std::min(lower_a, a);
+                continue;
+            }
+            ChaseWin &cw = R.w[R.nwin];
+            cw.a = a;
+            cw.wa = wa;
+            cw.p0 = gr.p0;
+            cw.nsteps = nsteps;
+            cw.kend = kend;
+            cw.nb = gr.nb;
+            cw.shift_off = gr.soff;
+            cw.slot = take_slot(C);
+            int tpos0 = gr.p0 - 3 * (gr.nb - 1);
+            cw.vig_lo = std::max(ktop, tpos0);
+            cw.vig_hi = std::min(kend, tpos0 + nsteps - 1);
+            if (cw.vig_hi - cw.vig_lo + 1 > WMAX) cw.vig_lo = cw.vig_hi - WMAX + 1;
+            R.nwin++;
+            gr.started = true;
+            gr.p0 += nsteps;
+            if (final_w) {
+                gr.done = true;
+                --remaining;
+            }
+            lower_a = a;
+        }
+        if (R.nwin == 0) return -98;
+        int pid = prof_begin(1, C.hi);
+        CK(launch_chase(V.H, V.ld, R, W.d_shift, W.d_shift + 2048, C.smlnum, W.ubuf, slot_ustride(), C.hi));
+        {
+            double fl = 0.0, by = 0.0;
+            for (int i = 0; i < R.nwin; ++i) {
+                // direct-reflector flops inside the window: about 11 per touched
+                // entry, 3 rows + 3 columns of A and 3 columns of U per reflector
+                double wa = R.w[i].wa;
+                fl += 11.0 * 3.0 * (2.0 * wa) * R.w[i].nb * R.w[i].nsteps;
+                by += 2.0 * 8.0 * wa * wa + 8.0 * wa * wa;
+            }
+            prof_end(pid, C.hi, fl, by);
+        }
+        if (C.stats) {
+            C.stats[6]++;
+            C.stats[7] += R.nwin;
+        }
+        // update products: all left products first (disjoint rows), then all
+        // right products (disjoint columns)
+        UpdBatch hiL = make_batch(), hiR = make_batch(), loL = make_batch(), loR = make_batch();
+        for (int i = 0; i < R.nwin; ++i) {
+            const ChaseWin &cw = R.w[i];
+            const double *Ut = slot_ptr(W, cw.slot);
+            int c0 = cw.a + cw.wa;
+            if (!C.two) {
+                add_job(hiL, V.H + cw.a + (int64_t)c0 * V.ld, V.ld, V.n - c0, cw.wa, Ut, 1);
+                add_job(hiR, V.H + (int64_t)cw.a * V.ld, V.ld, cw.a, cw.wa, Ut, 0);
+                if (V.Q) add_job(hiR, V.Q + (int64_t)cw.a * V.ldq, V.ldq, V.nq, cw.wa, Ut, 0);
+            } else {
+                int ncol_in = std::max(0, kbot - c0 + 1);
+                add_job(hiL, V.H + cw.a + (int64_t)c0 * V.ld, V.ld, ncol_in, cw.wa, Ut, 1);
+                add_job(loL, V.H + cw.a + (int64_t)(c0 + ncol_in) * V.ld, V.ld, V.n - c0 - ncol_in, cw.wa, Ut,
+                        1);
+                int nrow_in = std::max(0, cw.a - ktop);
+                add_job(hiR, V.H + ktop + (int64_t)cw.a * V.ld, V.ld, nrow_in, cw.wa, Ut, 0);
+                add_job(loR, V.H + (int64_t)cw.a * V.ld, V.ld, cw.a - nrow_in, cw.wa, Ut, 0);
+                if (V.Q) add_job(loR, V.Q + (int64_t)cw.a * V.ldq, V.ldq, V.nq, cw.wa, Ut, 0);
+            }
+        }
+        if (flush(hiL, C.hi, C)) return -1;
+        if (flush(hiR, C.hi, C)) return -1;
+        if (C.two) {
+            hipEvent_t e = next_event(W);
+            hipEventRecord(e, C.hi);
+            hipStreamWaitEvent(W.lo, e, 0);
+            if (flush(loL, W.lo, C)) return -1;
+            if (flush(loR, W.lo, C)) return -1;
+            for (int i = 0; i < R.nwin; ++i) release_slot(C, R.w[i].slot);
+        }
+    }
+    return 0;
+}
+
+// --------------------------------------------------------------------------
+// driver
+
+int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int *info_out);
+
+// AED step with a window larger than the LDS solver: recursive Schur form of
+// a copy of the window, corner deflation, Hessenberg restoration.
+int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd, int &ns, int &ncand)
+{
+    Workspace &W = *C.W;
+    if (ensure_depth(W, depth, w)) return -1;
+    int kwtop = kbot - w + 1;
+    double s = 0.0;
+    if (kwtop > ktop) {
+        CK(hipMemcpyAsync(&W.st_host->beta, V.H + kwtop + (int64_t)(kwtop - 1) * V.ld, sizeof(double),
+                          hipMemcpyDeviceToHost, C.hi));
+        CK(hipStreamSynchronize(C.hi));
+        s = W.st_host->beta;
+    }
+    double *T = W.wT[depth], *Vw = W.wV[depth], *Ut = W.wU[depth];
+    CK(launch_window_copy(V.H, V.ld, kwtop, w, T, w, Vw, w, C.hi));
+    Params Pi = C.P;
+    auto_ns_nw(w, Pi.ns, Pi.nw);
+    Pi.nw = std::min(std::max(Pi.nw, 48), MMAX);
+    Pi.ns = std::min(Pi.ns, std::max(2, (w / 4) & ~1));
+    Pi.itmax = C.P.itmax;
+    View Vi{T, w, w, Vw, w, w};
+    Ctx Ci = C;
+    Ci.two = false; // the window is small; keep its updates in order on one stream
+    int info = 0;
+    int rc = run(Ci, Vi, 0, w - 1, Pi, depth + 1, &info);
+    if (rc) return rc;
+    if (info > 0) {
+        nd = 0;
+        ns = w;
+        CK(launch_block_eigs(T, w, w, W.st_dev->cr, W.st_dev->ci, C.hi));
+        if (read_status(C, w)) return -1;
+        ncand = w;
+        return 0;
+    }
+    int wd = std::min(w, MMAX);
+    int slc = take_slot(C);
+    double *Utc = slot_ptr(W, slc);
+    release_slot(C, slc);
+    int pidc = prof_begin(3, C.hi);
+    CK(launch_corner_deflate(T, w, w, wd, Vw, w, s, C.smlnum, Utc, W.st_dev, C.hi));
+    prof_end(pidc, C.hi, 0.0, 0.0);
+    if (read_status(C, 0)) return -1;
+    int c0 = W.st_host->kwtop, wdd = W.st_host->nw;
+    ns = W.st_host->ns;
+    nd = W.st_host->nd;
+    {
+        UpdBatch b = make_batch();
+        add_job(b, T + (int64_t)c0 * w, w, c0, wdd, Utc, 0);
+        add_job(b, Vw + (int64_t)c0 * w, w, w, wdd, Utc, 0);
+        if (flush(b, C.hi, C)) return -1;
+    }
+    CK(launch_block_eigs(T, w, ns, W.st_dev->cr, W.st_dev->ci, C.hi));
+    ncand = ns;
+    if (nd > 0) {
+        double beta = 0.0;
+        if (ns > 1 && s != 0.0) {
+            int pidr = prof_begin(3, C.hi);
+            CK(launch_restore(T, w, w, ns, Vw, w, w, s, W.vbuf, W.st_dev, C.hi));
+            prof_end(pidr, C.hi, 10.0 / 3.0 * (double)ns * ns * ns + 4.0 * (double)w * ns * ns, 0.0);
+            CK(hipMemcpyAsync(&W.st_host->beta, &W.st_dev->beta, sizeof(double), hipMemcpyDeviceToHost, C.hi));
+        } else if (ns >= 1) {
+            CK(hipMemcpyAsync(&W.st_host->beta, Vw, sizeof(double), hipMemcpyDeviceToHost, C.hi));
+        }
+        if (read_status(C, ncand)) return -1;
+        if (ns > 1 && s != 0.0) beta = W.st_host->beta;
+        else if (ns >= 1) beta = s * W.st_host->beta;
+        // copy the window back (zeros below the subdiagonal) and set the new subdiagonal
+        CK(hipMemcpy2DAsync(V.H + kwtop + (int64_t)kwtop * V.ld, V.ld * sizeof(double), T, w * sizeof(double),
+                            w * sizeof(double), w, hipMemcpyDeviceToDevice, C.hi));
+        CK(launch_zero_lower(V.H + kwtop + (int64_t)kwtop * V.ld, V.ld, w, C.hi));
+        if (kwtop > ktop) {
+            W.st_host->beta = beta;
+            CK(hipMemcpyAsync(V.H + kwtop + (int64_t)(kwtop - 1) * V.ld, &W.st_host->beta, sizeof(double),
+                              hipMemcpyHostToDevice, C.hi));
+        }
+        int w16 = (w + 15) & ~15;
+        if (C.two && W.wU_pending[depth]) CK(hipStreamWaitEvent(C.hi, W.wU_ev[depth], 0));
+        CK(launch_transpose_pad(Vw, w, w, Ut, w16, C.hi));
+        int rc2 = apply_factor(C, V, ktop, kbot, kwtop, w, Ut);
+        if (rc2) return rc2;
+        if (C.two) {
+            CK(hipEventRecord(W.wU_ev[depth], W.lo));
+            W.wU_pending[depth] = 1;
+        }
+        // the host value for the subdiagonal must stay alive until the copy ran
+        CK(hipStreamSynchronize(C.hi));
+    } else {
+        if (read_status(C, ncand)) return -1;
+    }
+    return 0;
+}
+
+int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int *info_out)
+{
+    Workspace &W = *C.W;
+    IterStatus &S = *W.st_host;
+    int kbot = ihi;
+    int64_t it = 0;
+    int ndfl = 1;
+    std::vector<double> sr(2048), si(2048), cr, ci;
+    *info_out = 0;
+    while (kbot >= ilo) {
+        int ktop, nd = 0, ns = 0, ncand = 0, wwin = 0;
+        bool aed = false;
+        int nwp = std::min(P.nw, MMAX);
+        if (P.nw <= MMAX) {
+            int sl = take_slot(C);
+            double *Ut = slot_ptr(W, sl);
+            int pid = prof_begin(0, C.hi);
+            CK(launch_iter(V.H, V.ld, V.n, ilo, kbot, P.nw, P.nmin, C.smlnum, P.itmax, Ut, W.st_dev, C.hi));
+            prof_end(pid, C.hi, 0.0, 0.0);
+            if (C.stats) C.stats[6]++;
+            if (read_status(C, nwp)) return -1;
+            ktop = S.ktop;
+            if (S.kind == 0) {
+                if (S.info > 0) {
+                    *info_out = S.info;
+                    return 0;
+                }
+                if (C.stats) C.stats[4]++;
+                int rc = apply_factor(C, V, ktop, kbot, S.kwtop, S.nw, Ut);
+                release_slot(C, sl);
+                if (rc) return rc;
+                kbot = ktop - 1;
+                ndfl = 1;
+                continue;
+            }
+            aed = true;
+            nd = S.nd;
+            ns = S.ns;
+            ncand = S.ncand;
+            wwin = S.nw;
+            if (S.changed) {
+                int rc = apply_factor(C, V, ktop, kbot, S.kwtop, S.nw, Ut);
+                if (rc) return rc;
+            }
+            release_slot(C, sl);
+        } else {
+            CK(launch_find_block(V.H, V.ld, ilo, kbot, C.smlnum, W.st_dev, C.hi));
+            if (read_status(C, 0)) return -1;
+            ktop = S.ktop;
+            int nh = kbot - ktop + 1;
+            int wv = std::min(P.nw, nh);
+            if (nh <= P.nmin || wv <= MMAX) {
+                int sl = take_slot(C);
+                double *Ut = slot_ptr(W, sl);
+                int pid = prof_begin(0, C.hi);
+                CK(launch_iter(V.H, V.ld, V.n, ilo, kbot, wv, P.nmin, C.smlnum, P.itmax, Ut, W.st_dev, C.hi));
+                prof_end(pid, C.hi, 0.0, 0.0);
+                if (read_status(C, MMAX)) return -1;
+                if (S.kind == 0) {
+                    if (S.info > 0) {
+                        *info_out = S.info;
+                        return 0;
+                    }
+                    if (C.stats) C.stats[4]++;
+                    int rc = apply_factor(C, V, ktop, kbot, S.kwtop, S.nw, Ut);
+                    release_slot(C, sl);
+                    if (rc) return rc;
+                    kbot = ktop - 1;
+                    ndfl = 1;
+                    continue;
+                }
+                nd = S.nd;
+                ns = S.ns;
+                ncand = S.ncand;
+                wwin = S.nw;
+                if (S.changed) {
+                    int rc = apply_factor(C, V, ktop, kbot, S.kwtop, S.nw, Ut);
+                    if (rc) return rc;
+                }
+                release_slot(C, sl);
+            } else {
+                int rc = big_aed(C, V, ktop, kbot, wv, depth, nd, ns, ncand);
+                if (rc) return rc;
+                wwin = wv;
+            }
+            aed = true;
+        }
+        (void)aed;
+        if (++it > P.itmax) {
+            *info_out = kbot + 1;
+            return 0;
+        }
+        if (C.stats && depth == 0) {
+            C.stats[0]++;
+            C.stats[3] += nd;
+        }
+        cr.assign(S.cr, S.cr + ncand);
+        ci.assign(S.ci, S.ci + ncand);
+        kbot -= nd;
+        ndfl = (nd > 0) ? 1 : ndfl + 1;
+        if (nd > 0 && 100 * nd > P.nibble * wwin) continue;
+        if (kbot - ktop + 1 <= P.nmin) continue;
+        int nsh = 0;
+        if (ndfl % P.kexsh == 0) {
+            // Reading: exceptional shifts from the trailing subdiagonal
+            int want = P.ns;
+            if (want > kbot - ktop - 1) want = (kbot - ktop - 1) & ~1;
+            int cnt = std::min(want, kbot - ktop);
+            int lo_row = std::max(ktop, kbot - cnt - 2);
+            int rows = kbot - lo_row + 1;
+            std::vector<double> diag(rows), sub(rows);
+            // fetch the needed diagonal and subdiagonal entries
+            for (int i = 0; i < rows; ++i) {
+                int r = lo_row + i;
+                CK(hipMemcpyAsync(&diag[i], V.H + r + (int64_t)r * V.ld, sizeof(double), hipMemcpyDeviceToHost,
+                                  C.hi));
+                if (r > 0)
+                    CK(hipMemcpyAsync(&sub[i], V.H + r + (int64_t)(r - 1) * V.ld, sizeof(double),
+                                      hipMemcpyDeviceToHost, C.hi));
+                else
+                    sub[i] = 0.0;
+            }
+            CK(hipStreamSynchronize(C.hi));
+            for (int i = kbot; i >= ktop + 2 && nsh + 2 <= want; i -= 2) {
+                int li = i - lo_row;
+                if (li - 1 < 0) break;
+                double ss = std::fabs(sub[li]) + std::fabs(sub[li - 1]);
+                double a = 0.75 * ss + diag[li];
+                double w2 = ss * std::sqrt(0.4375);
+                sr[nsh] = a;
+                si[nsh] = w2;
+                sr[nsh + 1] = a;
+                si[nsh + 1] = -w2;
+                nsh += 2;
+            }
+        } else {
+            // Reading: bottommost candidates, conjugate pairs together, real
+            // shifts paired in order, an odd real left over dropped.
+            int nc = ncand;
+            int want = std::min(P.ns, nc);
+            int start = nc - want;
+            if (start > 0 && start < nc && ci[start] < 0.0) start++;
+            double rr[2];
+            int nr = 0;
+            for (int i = nc - 1; i >= start; --i) {
+                if (ci[i] != 0.0) {
+                    if (ci[i] < 0.0 && i - 1 >= start) {
+                        sr[nsh] = cr[i - 1];
+                        si[nsh] = ci[i - 1];
+                        sr[nsh + 1] = cr[i];
+                        si[nsh + 1] = ci[i];
+                        nsh += 2;
+                        --i;
+                    }
+                } else {
+                    rr[nr++] = cr[i];
+                    if (nr == 2) {
+                        sr[nsh] = rr[0];
+                        si[nsh] = 0.0;
+                        sr[nsh + 1] = rr[1];
+                        si[nsh + 1] = 0.0;
+                        nsh += 2;
+                        nr = 0;
+                    }
+                }
+            }
+            if (nsh < 2 || (nd > 0 && nsh < P.ns / 2)) continue;
+        }
+        if (nsh < 2) continue;
+        int rc = sweep(C, V, ktop, kbot, nsh, sr.data(), si.data());
+        if (rc) return rc;
+        if (C.stats && depth == 0) {
+            C.stats[1]++;
+            C.stats[2] += nsh;
+        }
+    }
+    return 0;
+}
+
+Params resolve(const hqr_params *pp, int n)
+{
+    hqr_params p;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        p = g_params;
+    }
+    if (pp) p = *pp;
+    Params P;
+    auto_ns_nw(n, P.ns, P.nw);
+    if (p.ns > 0) P.ns = p.ns & ~1;
+    if (p.nw > 0) P.nw = p.nw;
+    if (P.ns < 2) P.ns = 2;
+    P.nmin = p.nmin > 0 ? p.nmin : 75;
+    P.nmin = std::max(12, std::min(P.nmin, MMAX));
+    P.nibble = p.nibble > 0 ? p.nibble : 14;
+    P.kexsh = p.kexsh > 0 ? p.kexsh : 6;
+    P.itmax = p.itmax > 0 ? p.itmax : 30 * (int64_t)std::max(10, n);
+    P.window = p.window > 0 ? std::min(p.window, WMAX) : WMAX;
+    P.gsize = p.bulges_per_window > 0 ? std::min(p.bulges_per_window, GMAX) : GMAX;
+    P.streams = p.streams > 0 ? p.streams : 2;
+    if (P.nw < 2) P.nw = 2;
+    return P;
+}
+
+} // namespace
+
+extern "C" {
+
+int hqr_set_params(const hqr_params *p)
+{
+    if (!p) return -1;
+    if (p->ns < 0 || p->nw < 0 || p->nmin < 0 || p->window < 0 || p->defl_mode != 0) return -1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_params = *p;
+    return 0;
+}
+
+int hqr_get_params(hqr_params *p)
+{
+    if (!p) return -1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    *p = g_params;
+    return 0;
+}
+
+int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi, void *stream,
+                 const hqr_params *pp)
+{
+    for (int i = 0; i < 8; ++i) t_stats[i] = 0;
+    if (n < 0) return -3;
+    if (n == 0) return 0;
+    if (!H) return -1;
+    if (ld < std::max<int64_t>(1, n)) return -4;
+    if (!wr) return -5;
+    if (!wi) return -6;
+    if (n > (int64_t)INT32_MAX / 2) return -3;
+    if (pp && pp->defl_mode != 0) return -8;
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 16) return -1000;
+    Workspace &W = g_ws[dev];
+    int e = ensure_ws(W, dev);
+    if (e) return e;
+    Params P = resolve(pp, (int)n);
+    Ctx C;
+    C.W = &W;
+    C.hi = (hipStream_t)stream;
+    C.two = P.streams >= 2;
+    C.smlnum = DBL_MIN * ((double)n / DBL_EPSILON);
+    C.P = P;
+    C.stats = t_stats;
+    // argument check on the device: non-finite entries of the Hessenberg part
+    CK(hipMemsetAsync(W.flag, 0, sizeof(int), C.hi));
+    CK(launch_check_finite(H, ld, (int)n, W.flag, C.hi));
+    int flag = 0;
+    CK(hipMemcpyAsync(&W.st_host->pad, W.flag, sizeof(int), hipMemcpyDeviceToHost, C.hi));
+    CK(hipStreamSynchronize(C.hi));
+    flag = W.st_host->pad;
+    if (flag) return -1;
+    CK(launch_zero_lower(H, ld, (int)n, C.hi));
+    View V{H, ld, (int)n, Q, ld, Q ? (int)n : 0};
+    int info = 0;
+    int rc = run(C, V, 0, (int)n - 1, P, 0, &info);
+    if (rc) {
+        hipStreamSynchronize(W.lo);
+        return rc;
+    }
+    // join the deferred stream, then standardize and extract eigenvalues
+    if (C.two) {
+        hipEvent_t ev = next_event(W);
+        CK(hipEventRecord(ev, W.lo));
+        CK(hipStreamWaitEvent(C.hi, ev, 0));
+    }
+    if (W.fin_n < (size_t)n) {
+        if (W.fin) hipFree(W.fin);
+        CK(hipMalloc(&W.fin, sizeof(double) * 8 * (size_t)n));
+        W.fin_n = n;
+    }
+    int pidf = prof_begin(4, C.hi);
+    CK(launch_finalize_ws(H, ld, (int)n, Q, wr, wi, W.fin, C.hi));
+    prof_end(pidf, C.hi, 0.0, 0.0);
+    CK(hipStreamSynchronize(C.hi));
+    for (int i = 0; i < W.nslots; ++i) W.slot_used[i] = 0;
+    return info;
+}
+
+int hqr_schur(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi, void *stream)
+{
+    return hqr_schur_ex(H, Q, n, ld, wr, wi, stream, nullptr);
+}
+
+int hqr_last_stats(int64_t *stats, int len)
+{
+    if (!stats || len <= 0) return 0;
+    int m = std::min(len, 8);
+    for (int i = 0; i < m; ++i) stats[i] = t_stats[i];
+    return m;
+}
+
+int hqr_profile_enable(int on)
+{
+    g_prof_on = on != 0;
+    return 0;
+}
+
+int hqr_profile_reset(void)
+{
+    prof_collect();
+    for (int c = 0; c < NCLASS; ++c) {
+        g_prof_ms[c] = g_prof_flops[c] = g_prof_bytes[c] = 0.0;
+        g_prof_n[c] = 0;
+    }
+    return 0;
+}
+
+int hqr_profile_read(double *ms, int64_t *launches, double *flops, double *bytes, int nclass)
+{
+    if (!ms || !launches || !flops || !bytes || nclass <= 0) return -1;
+    prof_collect();
+    int m = std::min(nclass, NCLASS);
+    for (int c = 0; c < m; ++c) {
+        ms[c] = g_prof_ms[c];
+        launches[c] = g_prof_n[c];
+        flops[c] = g_prof_flops[c];
+        bytes[c] = g_prof_bytes[c];
+    }
+    return m;
+}
+
+int hqr_finalize(void)
+{
+    for (auto &W : g_ws) {
+        if (!W.init) continue;
+        hipSetDevice(W.dev);
+        hipDeviceSynchronize();
+        for (auto e : W.slot_ev) hipEventDestroy(e);
+        for (int i = 0; i < 64; ++i) hipEventDestroy(W.ev_pool[i]);
+        hipStreamDestroy(W.lo);
+        hipFree(W.st_dev);
+        hipHostFree(W.st_host);
+        hipHostFree(W.sh_host);
+        hipFree(W.d_shift);
+        hipFree(W.ubuf);
+        hipFree(W.fin);
+        hipFree(W.vbuf);
+        hipFree(W.flag);
+        for (auto e : W.wU_ev) hipEventDestroy(e);
+        for (size_t d = 0; d < W.wT.size(); ++d) {
+            hipFree(W.wT[d]);
+            hipFree(W.wV[d]);
+            hipFree(W.wU[d]);
+        }
+        W = Workspace();
+    }
+    return 0;
+}
+
+int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int32_t batch, double *wr,
+                      double *wi, const int64_t *eig_offsets, int32_t *info, void *stream)
+{
+    if (batch < 0) return -5;
+    if (batch == 0) return 0;
+    if (!H) return -1;
+    if (!offsets) return -3;
+    if (!n) return -4;
+    if (!wr) return -6;
+    if (!wi) return -7;
+    if (!eig_offsets) return -8;
+    if (!info) return -9;
+    CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, nullptr, (hipStream_t)stream));
+    return 0;
+}
+
+int hqr_eig_backward_batched(const double *T, const double *Q, int32_t n, int32_t batch, const double *wr,
+                             const double *wi, const double *gwr, const double *gwi, double *dH, int32_t hess_mask,
+                             void *stream)
+{
+    if (!T) return -1;
+    if (!Q) return -2;
+    if (n < 0 || n > MMAX) return -3;
+    if (batch < 0) return -4;
+    if (!wr) return -5;
+    if (!wi) return -6;
+    if (!gwr) return -7;
+    if (!gwi) return -8;
+    if (!dH) return -9;
+    if (n == 0 || batch == 0) return 0;
+    CK(launch_eig_backward(T, Q, n, batch, wr, wi, gwr, gwi, dH, hess_mask, (hipStream_t)stream));
+    return 0;
+}
+
+} // extern "C"

@@ -1,0 +1,62 @@
+"""C-ABI checks that need no GPU: libhqr.so loads and exports every entry point
+declared in include/hqr.h, and argument validation returns the documented
+codes before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "hqr.h")).read()
+    return sorted(set(re.findall(r"^\s*int\s+(hqr_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2007_03576_amd._lib import lib
+    return lib()
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ["hqr_schur", "hqr_schur_batched", "hqr_eig_backward_batched", "hqr_set_params"]:
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(L):
+    for s in declared_symbols():
+        assert hasattr(L, s), f"libhqr.so does not export {s}"
+
+
+def test_argument_validation_without_device_work(L):
+    buf = (ctypes.c_double * 4)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert L.hqr_schur(p, None, -1, 1, p, p, None) == -3
+    assert L.hqr_schur(None, None, 2, 2, p, p, None) == -1
+    assert L.hqr_schur(p, None, 3, 2, p, p, None) == -4
+    assert L.hqr_schur(p, None, 2, 2, None, p, None) == -5
+    assert L.hqr_schur(p, None, 2, 2, p, None, None) == -6
+    assert L.hqr_schur(p, None, 0, 1, p, p, None) == 0
+    assert L.hqr_schur_batched(p, None, p, p, -1, p, p, p, p, None) == -5
+    assert L.hqr_eig_backward_batched(p, p, 500, 1, p, p, p, p, p, 1, None) == -3
+
+
+def test_params_roundtrip_and_rejection(L):
+    from paper_2007_03576_amd._lib import HqrParams
+    old = HqrParams()
+    assert L.hqr_get_params(ctypes.byref(old)) == 0
+    hp = HqrParams()
+    hp.ns, hp.nw, hp.nmin = 64, 256, 60
+    assert L.hqr_set_params(ctypes.byref(hp)) == 0
+    got = HqrParams()
+    assert L.hqr_get_params(ctypes.byref(got)) == 0
+    assert (got.ns, got.nw, got.nmin) == (64, 256, 60)
+    bad = HqrParams()
+    bad.defl_mode = 1  # only the LAPACK-style conditions are implemented
+    assert L.hqr_set_params(ctypes.byref(bad)) == -1
+    assert L.hqr_set_params(ctypes.byref(old)) == 0
+    assert L.hqr_set_params(None) == -1
