@@ -214,3 +214,66 @@ def eig_offsets(sizes) -> np.ndarray:
     if len(sizes) > 1:
         e[1:] = np.cumsum(sizes[:-1])
     return e
+
+
+def hessenberg_reduce_torch(A):
+    """Householder reduction of a square device matrix to upper Hessenberg form
+    (input preparation for the large configurations, where the host reduction
+    would take minutes).  Returns the Hessenberg matrix with exact zeros below
+    the subdiagonal; the orthogonal factor is not formed."""
+    import torch
+    A = A.clone()
+    n = A.shape[0]
+    for k in range(n - 2):
+        x = A[k + 1:, k]
+        alpha = x[0].item()
+        tail = torch.linalg.vector_norm(x[1:]).item()
+        if tail == 0.0:
+            continue
+        nrm = float(np.hypot(alpha, tail))
+        beta = -nrm if alpha >= 0 else nrm
+        tau = (beta - alpha) / beta
+        v = x / (alpha - beta)
+        v[0] = 1.0
+        # left: rows k+1.., columns k..
+        w = torch.mv(A[k + 1:, k:].t(), v)
+        A[k + 1:, k:].addr_(v, w, alpha=-tau)
+        # right: all rows, columns k+1..
+        z = torch.mv(A[:, k + 1:], v)
+        A[:, k + 1:].addr_(z, v, alpha=-tau)
+        A[k + 2:, k] = 0.0
+        A[k + 1, k] = beta
+    return torch.triu(A, -1)
+
+
+def prescribed_hessenberg_device(n: int, seed: int = SEED, device="cuda"):
+    """prescribed_hessenberg built on the GPU with torch (Haar W by QR, A = W L W^T,
+    Householder Hessenberg reduction).  Returns (H row-major device tensor, eigenvalues)."""
+    import torch
+    g = rng(seed)
+    n_pairs = n // 4
+    n_real = n - 2 * n_pairs
+    reals, a, b = prescribed_spectrum(n_real, n_pairs, g)
+    sizes = np.array([1] * n_real + [2] * n_pairs)
+    order = g.permutation(len(sizes))
+    Z = torch.from_numpy(g.standard_normal((n, n))).to(device)
+    W, R = torch.linalg.qr(Z)
+    del Z
+    W = W * torch.sign(torch.diagonal(R)).where(torch.diagonal(R) != 0, torch.ones((), device=device, dtype=W.dtype))
+    del R
+    WL = torch.empty_like(W)
+    col = 0
+    for o in order:
+        if o < n_real:
+            WL[:, col] = W[:, col] * reals[o]
+            col += 1
+        else:
+            j = o - n_real
+            w1, w2 = W[:, col], W[:, col + 1]
+            WL[:, col] = a[j] * w1 - b[j] * w2
+            WL[:, col + 1] = b[j] * w1 + a[j] * w2
+            col += 2
+    A = WL @ W.t()
+    del WL, W
+    H = hessenberg_reduce_torch(A)
+    return H, eigs_from_spectrum(reals, a, b)

@@ -42,7 +42,10 @@ extern "C" {
  *   bulges_per_window  bulges in one window chain
  *   defl_mode  0 = LAPACK-style conditions (the only mode implemented)
  *   streams    1 = everything on the caller's stream; 2 = updates outside the
- *              active block and to Q on a second stream (Sec. 3.3 priorities) */
+ *              active block and to Q on a second stream (Sec. 3.3 priorities)
+ *   small_shifts  shifts per sweep of the one-workgroup solver (2 = Francis
+ *              double shift; 4..16 = chains of bulges shifted by the
+ *              eigenvalues of the trailing block, Sec. 2.3) */
 typedef struct hqr_params {
     int ns, nw, nmin, nibble, kexsh;
     int64_t itmax;
@@ -50,6 +53,7 @@ typedef struct hqr_params {
     int defl_mode;
     double defl_thold;
     int streams;
+    int small_shifts;
 } hqr_params;
 
 /* Process-wide defaults used by later calls.  Returns 0 or -1 (NULL / invalid). */
@@ -72,10 +76,12 @@ int hqr_schur(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *w
 int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi, void *stream,
                  const hqr_params *p);
 
-/* Batched form for many small independent problems (one persistent launch,
- * one workgroup per matrix).  Matrix i has order n[i] <= 96, stored packed
- * column major at H + offsets[i] with leading dimension n[i]; Q likewise
- * (Q may be NULL; otherwise it must hold Q0, e.g. identity, on entry).
+/* Batched form for many small independent problems (persistent launches,
+ * one workgroup per matrix).  Matrix i has order n[i], stored packed column
+ * major at H + offsets[i] with leading dimension n[i]; Q likewise (Q may be
+ * NULL; otherwise it must hold Q0, e.g. identity, on entry, and receives
+ * Q0*Qhat).  Orders <= 96 are solved with matrix and factor in LDS, larger
+ * ones in place in global memory (the L2-resident path).
  * Eigenvalues of matrix i go to wr/wi + eig_offsets[i]; info[i] receives the
  * per-matrix code (0 or +i).  offsets, n, eig_offsets, info are device
  * arrays.  Fully asynchronous on `stream`; allocates nothing on the device. */
@@ -83,7 +89,7 @@ int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_
                       double *wr, double *wi, const int64_t *eig_offsets, int32_t *info, void *stream);
 
 /* Backward pass of the eigenvalues for a batch of Schur forms (T_i, Q_i) of
- * equal order n <= 96 stored back to back (T + i*n*n).  Given the cotangents
+ * equal order n stored back to back, column major (T + i*n*n).  Given the cotangents
  * g = dL/dRe(lambda) + i dL/dIm(lambda) (gwr/gwi, n per matrix, ordered as
  * wr/wi), writes dH_i = Re(conj(Y) diag(conj(g)/(y^H x)) X^T) where X, Y hold
  * the right and left eigenvectors (Sec. 2 eigenvector relation x = Q y);

@@ -80,7 +80,7 @@ struct UpdBatch {
 // then either reduce a small block to Schur form or perform an AED step with
 // window nw (<= MMAX).  Writes the factor (transposed, padded) to Ut.
 hipError_t launch_iter(double *H, int64_t ld, int n, int ilo, int kbot, int nw, int nmin,
-                       double smlnum, int64_t itmax, double *Ut, IterStatus *st, hipStream_t s);
+                       double smlnum, int64_t itmax, double *Ut, IterStatus *st, hipStream_t s, int nsmall);
 // Locate the top of the active block only (st->ktop).
 hipError_t launch_find_block(double *H, int64_t ld, int ilo, int kbot, double smlnum, IterStatus *st,
                              hipStream_t s);
@@ -110,7 +110,7 @@ hipError_t launch_zero_lower(double *H, int64_t ld, int n, hipStream_t s);
 hipError_t launch_transpose_pad(const double *V, int64_t ldv, int K, double *Ut, int K16,
                                 hipStream_t s);
 hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch,
-                          double *wr, double *wi, const int64_t *eoff, int32_t *info, double *logbuf,
+                          double *wr, double *wi, const int64_t *eoff, int32_t *info, int nsmall,
                           hipStream_t s);
 hipError_t launch_eig_backward(const double *T, const double *Q, int n, int batch, const double *wr,
                                const double *wi, const double *gwr, const double *gwi, double *dH,

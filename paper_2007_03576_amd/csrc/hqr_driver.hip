@@ -29,7 +29,7 @@ using namespace hqr;
 namespace {
 
 std::mutex g_mu;
-hqr_params g_params = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0.0, 0};
+hqr_params g_params = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0.0, 0, 0};
 thread_local int64_t t_stats[8];
 
 struct Params {
@@ -37,6 +37,7 @@ struct Params {
     int64_t itmax;
     int window, gsize;
     int streams;
+    int nsmall; // shifts per multishift sweep of the one-workgroup solver (2 = double shift)
 };
 
 // Reading of automatic parameters: LAPACK's documented shift-count table and
@@ -617,7 +618,7 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
             int sl = take_slot(C);
             double *Ut = slot_ptr(W, sl);
             int pid = prof_begin(0, C.hi);
-            CK(launch_iter(V.H, V.ld, V.n, ilo, kbot, P.nw, P.nmin, C.smlnum, P.itmax, Ut, W.st_dev, C.hi));
+            CK(launch_iter(V.H, V.ld, V.n, ilo, kbot, P.nw, P.nmin, C.smlnum, P.itmax, Ut, W.st_dev, C.hi, P.nsmall));
             prof_end(pid, C.hi, 0.0, 0.0);
             if (C.stats) C.stats[6]++;
             if (read_status(C, nwp)) return -1;
@@ -655,7 +656,7 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
                 int sl = take_slot(C);
                 double *Ut = slot_ptr(W, sl);
                 int pid = prof_begin(0, C.hi);
-                CK(launch_iter(V.H, V.ld, V.n, ilo, kbot, wv, P.nmin, C.smlnum, P.itmax, Ut, W.st_dev, C.hi));
+                CK(launch_iter(V.H, V.ld, V.n, ilo, kbot, wv, P.nmin, C.smlnum, P.itmax, Ut, W.st_dev, C.hi, P.nsmall));
                 prof_end(pid, C.hi, 0.0, 0.0);
                 if (read_status(C, MMAX)) return -1;
                 if (S.kind == 0) {
@@ -800,6 +801,7 @@ Params resolve(const hqr_params *pp, int n)
     P.window = p.window > 0 ? std::min(p.window, WMAX) : WMAX;
     P.gsize = p.bulges_per_window > 0 ? std::min(p.bulges_per_window, GMAX) : GMAX;
     P.streams = p.streams > 0 ? p.streams : 2;
+    P.nsmall = p.small_shifts > 0 ? std::min(p.small_shifts, 16) & ~1 : 2;
     if (P.nw < 2) P.nw = 2;
     return P;
 }
@@ -969,7 +971,13 @@ int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_
     if (!wi) return -7;
     if (!eig_offsets) return -8;
     if (!info) return -9;
-    CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, nullptr, (hipStream_t)stream));
+    hqr_params gp;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        gp = g_params;
+    }
+    int nsmall = gp.small_shifts > 0 ? std::min(gp.small_shifts, 16) & ~1 : 2;
+    CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, nsmall, (hipStream_t)stream));
     return 0;
 }
 
@@ -979,7 +987,7 @@ int hqr_eig_backward_batched(const double *T, const double *Q, int32_t n, int32_
 {
     if (!T) return -1;
     if (!Q) return -2;
-    if (n < 0 || n > MMAX) return -3;
+    if (n < 0 || n > 8192) return -3;
     if (batch < 0) return -4;
     if (!wr) return -5;
     if (!wi) return -6;

@@ -26,18 +26,24 @@ namespace hqr {
 
 constexpr double kU = 2.220446049250313080847e-16; // unit roundoff 2^-52
 
-struct Smem {
-    double A[MMAX * LDM];
-    double Z[LDM * LDM];          // one spare row for a carried spike
+// Small per-workgroup state used by every solver piece.
+struct SmemCore {
     double bv1[GMAX], bv2[GMAX], btau[GMAX];
     int bk[GMAX], bm[GMAX], bc0[GMAX];
     double sr[2 * GMAX], si[2 * GMAX];
     double red[NT / 64];
     double G[16];
     double Dn[16];
-    double vec[LDM];
     double sc[8];
     int ic[8];
+    double shb[16 * 16]; // trailing block whose eigenvalues become the shifts of a multishift sweep
+};
+
+// LDS-resident matrix and accumulated factor for orders <= MMAX.
+struct Smem : SmemCore {
+    double A[MMAX * LDM];
+    double Z[LDM * LDM];          // one spare row for a carried spike
+    double vec[LDM];
     unsigned char vflag[WMAX];
 };
 
@@ -163,7 +169,7 @@ __device__ inline void shift_column(const double *A, int lda, int kt, int kb, do
 // ---------------------------------------------------------------------------
 // block-level helpers (all threads call them)
 
-__device__ inline double block_sum(Smem &S, double v)
+__device__ inline double block_sum(SmemCore &S, double v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     int w = threadIdx.x >> 6;
@@ -175,7 +181,7 @@ __device__ inline double block_sum(Smem &S, double v)
     return t;
 }
 
-__device__ inline double block_max(Smem &S, double v)
+__device__ inline double block_max(SmemCore &S, double v)
 {
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
     int w = threadIdx.x >> 6;
@@ -192,10 +198,12 @@ __device__ inline double block_max(Smem &S, double v)
 // p0 + t - 3b at step t and acts when ktop-1 <= k <= kend (a reflector at k
 // acts on rows/cols k+1..k+3).  Left application: local columns up to colhi.
 // Right application: local rows 0..min(k+4,kbot).  Z (nz rows) accumulates.
-__device__ void chain_chase(Smem &S, double *A, int lda, int off, int ktop, int kbot, int p0, int nsteps,
+__device__ void chain_chase(SmemCore &S, double *A, int lda, int off, int ktop, int kbot, int p0, int nsteps,
                             int kend, int nb, int colhi, double *Z, int ldz, int nz)
 {
     const int tid = threadIdx.x;
+    const int tpb = NT / nb; // threads per bulge in the apply phases
+    const int myb = tid / tpb, mys = tid - myb * tpb;
     for (int t = 0; t < nsteps; ++t) {
         if (tid < nb) {
             int b = tid;
@@ -229,52 +237,46 @@ __device__ void chain_chase(Smem &S, double *A, int lda, int off, int ktop, int 
             S.bm[b] = m;
         }
         __syncthreads();
-        // left: rows kl+1..kl+m, columns bc0..colhi
-        for (int it = tid; it < nb * LDM; it += NT) {
-            int b = it / LDM, c = it - b * LDM;
-            int m = S.bm[b];
-            if (m == 0 || c < S.bc0[b] || c > colhi) continue;
-            double tau = S.btau[b];
-            if (tau == 0.0) continue;
-            int r = S.bk[b] + 1;
-            double v1 = S.bv1[b], v2 = S.bv2[b];
-            double *col = A + c * lda + r;
-            double a0 = col[0], a1 = col[1];
-            double a2 = (m == 3) ? col[2] : 0.0;
-            double s = tau * (a0 + v1 * a1 + v2 * a2);
-            col[0] = a0 - s;
-            col[1] = a1 - s * v1;
-            if (m == 3) col[2] = a2 - s * v2;
+        // left: rows kl+1..kl+m, columns bc0..colhi (tpb threads per bulge)
+        if (myb < nb && S.bm[myb] != 0 && S.btau[myb] != 0.0) {
+            const int m = S.bm[myb];
+            const int r = S.bk[myb] + 1;
+            const double tau = S.btau[myb], v1 = S.bv1[myb], v2 = S.bv2[myb];
+            for (int c = S.bc0[myb] + mys; c <= colhi; c += tpb) {
+                double *col = A + c * lda + r;
+                double a0 = col[0], a1 = col[1];
+                double a2 = (m == 3) ? col[2] : 0.0;
+                double s = tau * (a0 + v1 * a1 + v2 * a2);
+                col[0] = a0 - s;
+                col[1] = a1 - s * v1;
+                if (m == 3) col[2] = a2 - s * v2;
+            }
         }
         __syncthreads();
-        // right: columns kl+1..kl+m, rows 0..min(kl+4, kbot-off) of A and all rows of Z
-        for (int it = tid; it < nb * 2 * LDM; it += NT) {
-            int b = it / (2 * LDM), r = it - b * (2 * LDM);
-            int m = S.bm[b];
-            if (m == 0) continue;
-            double tau = S.btau[b];
-            if (tau == 0.0) continue;
-            int kl = S.bk[b];
-            double *M;
-            int ld;
-            if (r < LDM) {
-                int rmax = min(kl + 4, kbot - off);
-                if (r > rmax) continue;
-                M = A + r;
-                ld = lda;
-            } else {
-                r -= LDM;
-                if (r >= nz) continue;
-                M = Z + r;
-                ld = ldz;
+        // right: columns kl+1..kl+m over rows 0..min(kl+4, kbot-off) of A and all rows of Z
+        if (myb < nb && S.bm[myb] != 0 && S.btau[myb] != 0.0) {
+            const int m = S.bm[myb];
+            const int kl = S.bk[myb];
+            const double tau = S.btau[myb], v1 = S.bv1[myb], v2 = S.bv2[myb];
+            const int rmax = min(kl + 4, kbot - off);
+            const int total = rmax + 1 + nz;
+            for (int r = mys; r < total; r += tpb) {
+                double *M;
+                int ld;
+                if (r <= rmax) {
+                    M = A + r;
+                    ld = lda;
+                } else {
+                    M = Z + (r - rmax - 1);
+                    ld = ldz;
+                }
+                double a0 = M[(kl + 1) * ld], a1 = M[(kl + 2) * ld];
+                double a2 = (m == 3) ? M[(kl + 3) * ld] : 0.0;
+                double s = tau * (a0 + v1 * a1 + v2 * a2);
+                M[(kl + 1) * ld] = a0 - s;
+                M[(kl + 2) * ld] = a1 - s * v1;
+                if (m == 3) M[(kl + 3) * ld] = a2 - s * v2;
             }
-            double v1 = S.bv1[b], v2 = S.bv2[b];
-            double a0 = M[(kl + 1) * ld], a1 = M[(kl + 2) * ld];
-            double a2 = (m == 3) ? M[(kl + 3) * ld] : 0.0;
-            double s = tau * (a0 + v1 * a1 + v2 * a2);
-            M[(kl + 1) * ld] = a0 - s;
-            M[(kl + 2) * ld] = a1 - s * v1;
-            if (m == 3) M[(kl + 3) * ld] = a2 - s * v2;
         }
         __syncthreads();
     }
@@ -282,7 +284,7 @@ __device__ void chain_chase(Smem &S, double *A, int lda, int off, int ktop, int 
 
 // Largest l in (lo,hi] whose subdiagonal A[l,l-1] is zero or negligible
 // (then set to zero); lo if there is none.
-__device__ int find_split(Smem &S, double *A, int lda, int lo, int hi, double smlnum)
+__device__ int find_split(SmemCore &S, double *A, int lda, int lo, int hi, double smlnum)
 {
     if (threadIdx.x == 0) S.ic[0] = lo;
     __syncthreads();
@@ -302,7 +304,7 @@ __device__ int find_split(Smem &S, double *A, int lda, int lo, int hi, double sm
 
 // Standardize the 2x2 block at (k,k+1): rows k,k+1 over columns k..ncol-1,
 // columns over rows 0..k+1, Z columns over nz rows.  Returns 1 for a complex pair.
-__device__ int std_block(Smem &S, double *A, int lda, int ncol, double *Z, int ldz, int nz, int k)
+__device__ int std_block(SmemCore &S, double *A, int lda, int ncol, double *Z, int ldz, int nz, int k)
 {
     for (int pass = 0; pass < 3; ++pass) {
         if (threadIdx.x == 0) {
@@ -358,10 +360,50 @@ __device__ int std_block(Smem &S, double *A, int lda, int ncol, double *Z, int l
     return A[(k + 1) + k * lda] != 0.0;
 }
 
-// Francis double-shift QR on the whole LDS matrix A (order m, full T), Z accumulates.
+// One Francis double-shift iteration on the active block [l,i] (full T and Z):
+// shifts from the trailing 2x2 (exceptional shifts at iterations 10 and 20).
+__device__ void ds_step(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, int l, int i, int its)
+{
+    if (threadIdx.x == 0) {
+        double a, b, c, d;
+        if (its == 10) {
+            double ss = fabs(A[(l + 1) + l * lda]) + fabs(A[(l + 2) + (l + 1) * lda]);
+            a = 0.75 * ss + A[l + l * lda];
+            b = -0.4375 * ss;
+            c = ss;
+            d = a;
+        } else if (its == 20) {
+            double ss = fabs(A[i + (i - 1) * lda]) + fabs(A[(i - 1) + (i - 2) * lda]);
+            a = 0.75 * ss + A[i + i * lda];
+            b = -0.4375 * ss;
+            c = ss;
+            d = a;
+        } else {
+            a = A[(i - 1) + (i - 1) * lda];
+            b = A[(i - 1) + i * lda];
+            c = A[i + (i - 1) * lda];
+            d = A[i + i * lda];
+        }
+        double r1, i1, r2, i2;
+        eig2x2(a, b, c, d, r1, i1, r2, i2);
+        if (i1 == 0.0) {
+            double hii = A[i + i * lda];
+            double pick = (fabs(r1 - hii) <= fabs(r2 - hii)) ? r1 : r2;
+            r1 = r2 = pick;
+        }
+        S.sr[0] = r1;
+        S.si[0] = i1;
+        S.sr[1] = r2;
+        S.si[1] = i2;
+    }
+    __syncthreads();
+    chain_chase(S, A, lda, 0, l, i, l - 1, (i - 2) - (l - 1) + 1, i - 2, 1, m - 1, Z, ldz, nz);
+}
+
+// Francis double-shift QR on the whole matrix A (order m, full T), Z accumulates.
 // Returns 0 or 1 + the bottom row of the block that did not converge.
-__device__ int qr_small(Smem &S, double *A, int lda, int m, double *Z, int ldz, int nz, double smlnum,
-                        int64_t itmax_in)
+__device__ int qr_ds(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, double smlnum,
+                     int64_t itmax_in)
 {
     int64_t itmax = 30 * (int64_t)max(10, m);
     if (itmax_in > 0 && itmax_in < itmax) itmax = itmax_in;
@@ -373,40 +415,98 @@ __device__ int qr_small(Smem &S, double *A, int lda, int m, double *Z, int ldz, 
             l = find_split(S, A, lda, 0, i, smlnum);
             if (l >= i - 1) break;
             if (total >= itmax) return i + 1;
-            if (threadIdx.x == 0) {
-                double a, b, c, d;
-                if (its == 10) {
-                    double ss = fabs(A[(l + 1) + l * lda]) + fabs(A[(l + 2) + (l + 1) * lda]);
-                    a = 0.75 * ss + A[l + l * lda];
-                    b = -0.4375 * ss;
-                    c = ss;
-                    d = a;
-                } else if (its == 20) {
-                    double ss = fabs(A[i + (i - 1) * lda]) + fabs(A[(i - 1) + (i - 2) * lda]);
-                    a = 0.75 * ss + A[i + i * lda];
-                    b = -0.4375 * ss;
-                    c = ss;
-                    d = a;
-                } else {
-                    a = A[(i - 1) + (i - 1) * lda];
-                    b = A[(i - 1) + i * lda];
-                    c = A[i + (i - 1) * lda];
-                    d = A[i + i * lda];
+            ds_step(S, A, lda, m, Z, ldz, nz, l, i, its);
+            ++its;
+            ++total;
+        }
+        if (l == i) {
+            i -= 1;
+        } else {
+            std_block(S, A, lda, m, Z, ldz, nz, i - 1);
+            i -= 2;
+        }
+    }
+    return 0;
+}
+
+// Small-block QR with multishift sweeps: when the active block is large
+// enough, the eigenvalues of its trailing ns x ns block (ns <= nsmax <= 16)
+// become the shifts of a chain of ns/2 tightly coupled bulges chased through
+// the block in one pass (Sec. 2.3); otherwise, and at the exceptional-shift
+// iterations, a double-shift step.  nsmax <= 2 gives the plain Francis QR.
+__device__ int qr_small(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, double smlnum,
+                        int64_t itmax_in, int nsmax = 2)
+{
+    if (nsmax <= 2) return qr_ds(S, A, lda, m, Z, ldz, nz, smlnum, itmax_in);
+    nsmax = min(nsmax, 16) & ~1;
+    int64_t itmax = 30 * (int64_t)max(10, m);
+    if (itmax_in > 0 && itmax_in < itmax) itmax = itmax_in;
+    int64_t total = 0;
+    int i = m - 1;
+    while (i >= 0) {
+        int its = 0, l;
+        for (;;) {
+            l = find_split(S, A, lda, 0, i, smlnum);
+            if (l >= i - 1) break;
+            if (total >= itmax) return i + 1;
+            const int nh = i - l + 1;
+            int ns = min(nsmax, (nh / 4) & ~1);
+            int nsh = 0;
+            if (ns >= 4 && its != 10 && its != 20) {
+                const int j0 = i - ns + 1;
+                for (int it = threadIdx.x; it < ns * ns; it += NT) {
+                    int r = it % ns, c = it / ns;
+                    S.shb[r + c * ns] = (r <= c + 1) ? A[(j0 + r) + (j0 + c) * lda] : 0.0;
                 }
-                double r1, i1, r2, i2;
-                eig2x2(a, b, c, d, r1, i1, r2, i2);
-                if (i1 == 0.0) {
-                    double hii = A[i + i * lda];
-                    double pick = (fabs(r1 - hii) <= fabs(r2 - hii)) ? r1 : r2;
-                    r1 = r2 = pick;
+                __syncthreads();
+                int inf = qr_ds(S, S.shb, ns, ns, nullptr, 0, 0, smlnum, 0);
+                if (threadIdx.x == 0) {
+                    // pair the eigenvalues of the converged part, bottom first
+                    int cnt = 0;
+                    double rr = 0.0;
+                    bool have = false;
+                    int k = ns - 1;
+                    while (k >= inf && cnt + 2 <= 2 * GMAX) {
+                        bool two = (k >= 1 && k - 1 >= inf && S.shb[k + (k - 1) * ns] != 0.0);
+                        if (two) {
+                            double r1, i1, r2, i2;
+                            eig2x2(S.shb[(k - 1) + (k - 1) * ns], S.shb[(k - 1) + k * ns], S.shb[k + (k - 1) * ns],
+                                   S.shb[k + k * ns], r1, i1, r2, i2);
+                            S.sr[cnt] = r1;
+                            S.si[cnt] = i1;
+                            S.sr[cnt + 1] = r2;
+                            S.si[cnt + 1] = i2;
+                            cnt += 2;
+                            k -= 2;
+                        } else {
+                            double v = S.shb[k + k * ns];
+                            if (have) {
+                                S.sr[cnt] = rr;
+                                S.si[cnt] = 0.0;
+                                S.sr[cnt + 1] = v;
+                                S.si[cnt + 1] = 0.0;
+                                cnt += 2;
+                                have = false;
+                            } else {
+                                rr = v;
+                                have = true;
+                            }
+                            k -= 1;
+                        }
+                    }
+                    S.ic[4] = cnt;
                 }
-                S.sr[0] = r1;
-                S.si[0] = i1;
-                S.sr[1] = r2;
-                S.si[1] = i2;
+                __syncthreads();
+                nsh = S.ic[4];
+                __syncthreads();
             }
-            __syncthreads();
-            chain_chase(S, A, lda, 0, l, i, l - 1, (i - 2) - (l - 1) + 1, i - 2, 1, m - 1, Z, ldz, nz);
+            if (nsh >= 4) {
+                const int nb = nsh / 2;
+                chain_chase(S, A, lda, 0, l, i, l - 1, (i - 2) - (l - 1) + 1 + 3 * (nb - 1), i - 2, nb, m - 1, Z,
+                            ldz, nz);
+            } else {
+                ds_step(S, A, lda, m, Z, ldz, nz, l, i, its);
+            }
             ++its;
             ++total;
         }
@@ -614,7 +714,7 @@ __device__ bool swap_transform(const double *T, int ldt, int j, int p, int q, do
 
 // Exchange the blocks of sizes p and q at row j of the LDS matrix T (order nt);
 // Z (nz rows) accumulates.  Returns 0 on success, 1 if rejected.
-__device__ int swap_blocks(Smem &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int j, int p,
+__device__ int swap_blocks(SmemCore &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int j, int p,
                            int q, double smlnum)
 {
     int m = p + q;
@@ -675,7 +775,7 @@ __device__ int swap_blocks(Smem &S, double *T, int ldt, int nt, double *Z, int l
 
 // Move the block starting at ifst up to ilst.  Returns 0, or 1 when a swap was
 // rejected or a 2x2 block split (the reordering halts, Schur form stays valid).
-__device__ int move_block_up(Smem &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int ifst,
+__device__ int move_block_up(SmemCore &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int ifst,
                              int ilst, double smlnum)
 {
     int here = ifst;
@@ -694,7 +794,7 @@ __device__ int move_block_up(Smem &S, double *T, int ldt, int nt, double *Z, int
 // Bottom-up deflation test of the candidates of the quasi-triangular T
 // (order nt) with spike entries sp_k = spscale * Z[sprow + k*ldz]; failures
 // move to the top.  Returns the number of undeflated leading rows.
-__device__ int aed_deflate(Smem &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int sprow,
+__device__ int aed_deflate(SmemCore &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int sprow,
                            double spscale, int ilst, double smlnum)
 {
     int ns = nt;
@@ -886,7 +986,7 @@ __global__ void __launch_bounds__(NT) k_find_block(double *H, int64_t ld, int il
 }
 
 __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int ilo, int kbot, int nw, int nmin,
-                                             double smlnum, int64_t itmax, double *Ut, IterStatus *st)
+                                             double smlnum, int64_t itmax, double *Ut, IterStatus *st, int nsmall)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem &S = *reinterpret_cast<Smem *>(smem_raw);
@@ -939,7 +1039,7 @@ __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int i
     }
     identity_lds(S.Z, LDM, m, m);
     __syncthreads();
-    int info = qr_small(S, S.A, LDM, m, S.Z, LDM, m, smlnum, itmax);
+    int info = qr_small(S, S.A, LDM, m, S.Z, LDM, m, smlnum, itmax, nsmall);
     int ns = 0, nd = m;
     double beta = 0.0;
     if (!small) {
@@ -1339,12 +1439,12 @@ static hipError_t prep(const void *fn)
 }
 
 hipError_t launch_iter(double *H, int64_t ld, int n, int ilo, int kbot, int nw, int nmin, double smlnum,
-                       int64_t itmax, double *Ut, IterStatus *st, hipStream_t s)
+                       int64_t itmax, double *Ut, IterStatus *st, hipStream_t s, int nsmall)
 {
     hipError_t e = prep((const void *)k_iter);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_iter, dim3(1), dim3(NT), smem_bytes(), s, H, ld, n, ilo, kbot, nw, nmin, smlnum,
-                       itmax, Ut, st);
+                       itmax, Ut, st, nsmall);
     return hipGetLastError();
 }
 
@@ -1442,15 +1542,16 @@ hipError_t launch_finalize_ws(double *H, int64_t ld, int n, double *Q, double *w
 
 __global__ void __launch_bounds__(NT) k_batched(double *H, double *Q, const int64_t *offs, const int32_t *nn,
                                                 int batch, double *wr, double *wi, const int64_t *eoff,
-                                                int32_t *info)
+                                                int32_t *info, int nsmall)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem &S = *reinterpret_cast<Smem *>(smem_raw);
     const int tid = threadIdx.x;
     for (int b = blockIdx.x; b < batch; b += gridDim.x) {
         const int n = nn[b];
-        if (n <= 0 || n > MMAX) {
-            if (tid == 0) info[b] = (n == 0) ? 0 : -4;
+        if (n > MMAX) continue; // global tier
+        if (n <= 0) {
+            if (tid == 0) info[b] = 0;
             continue;
         }
         double *A = H + offs[b];
@@ -1461,7 +1562,7 @@ __global__ void __launch_bounds__(NT) k_batched(double *H, double *Q, const int6
         identity_lds(S.Z, LDM, n, n);
         __syncthreads();
         const double smlnum = DBL_MIN * ((double)n / kU);
-        int inf = qr_small(S, S.A, LDM, n, S.Z, LDM, n, smlnum, 0);
+        int inf = qr_small(S, S.A, LDM, n, S.Z, LDM, n, smlnum, 0, nsmall);
         __syncthreads();
         for (int it = tid; it < n * n; it += NT) {
             int r = it % n, c = it / n;
@@ -1514,28 +1615,73 @@ __global__ void __launch_bounds__(NT) k_batched(double *H, double *Q, const int6
     }
 }
 
-hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch, double *wr,
-                          double *wi, const int64_t *eoff, int32_t *info, double *logbuf, hipStream_t s)
+// Orders above the LDS limit: the same solver with the matrix and Q in global
+// memory (L2 resident); small LDS footprint, two workgroups per CU.
+__global__ void __launch_bounds__(NT) k_batched_global(double *H, double *Q, const int64_t *offs,
+                                                       const int32_t *nn, int batch, double *wr, double *wi,
+                                                       const int64_t *eoff, int32_t *info, int nsmall)
 {
-    (void)logbuf;
+    __shared__ SmemCore S;
+    const int tid = threadIdx.x;
+    for (int b = blockIdx.x; b < batch; b += gridDim.x) {
+        const int n = nn[b];
+        if (n <= MMAX) continue;
+        double *A = H + offs[b];
+        for (int it = tid; it < n * n; it += NT) {
+            int r = it % n, c = it / n;
+            if (r > c + 1) A[it] = 0.0;
+        }
+        double *Z = Q ? Q + offs[b] : nullptr;
+        __syncthreads();
+        const double smlnum = DBL_MIN * ((double)n / kU);
+        int inf = qr_small(S, A, n, n, Z, n, Z ? n : 0, smlnum, 0, nsmall);
+        __syncthreads();
+        if (tid == 0) {
+            double *er = wr + eoff[b], *ei = wi + eoff[b];
+            int k = 0;
+            while (k < n) {
+                bool two = (k + 1 < n && A[(k + 1) + (int64_t)k * n] != 0.0);
+                if (!two) {
+                    er[k] = A[k + (int64_t)k * n];
+                    ei[k] = 0.0;
+                    k += 1;
+                } else {
+                    double r1, i1, r2, i2;
+                    eig2x2(A[k + (int64_t)k * n], A[k + (int64_t)(k + 1) * n], A[(k + 1) + (int64_t)k * n],
+                           A[(k + 1) + (int64_t)(k + 1) * n], r1, i1, r2, i2);
+                    if (i1 < 0.0) {
+                        double t = i1;
+                        i1 = i2;
+                        i2 = t;
+                    }
+                    er[k] = r1;
+                    ei[k] = i1;
+                    er[k + 1] = r2;
+                    ei[k + 1] = i2;
+                    k += 2;
+                }
+            }
+            info[b] = inf;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch, double *wr,
+                          double *wi, const int64_t *eoff, int32_t *info, int nsmall, hipStream_t s)
+{
     hipError_t e = prep((const void *)k_batched);
     if (e != hipSuccess) return e;
     int dev = 0, ncu = 256;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     int grid = std::min(batch, std::max(ncu, 1));
+    // orders > MMAX first (they dominate the time), then the LDS tier
+    hipLaunchKernelGGL(k_batched_global, dim3(std::min(batch, 2 * std::max(ncu, 1))), dim3(NT), 0, s, H, Q,
+                       offsets, n, batch, wr, wi, eoff, info, nsmall);
     hipLaunchKernelGGL(k_batched, dim3(grid), dim3(NT), smem_bytes(), s, H, Q, offsets, n, batch, wr, wi, eoff,
-                       info);
+                       info, nsmall);
     return hipGetLastError();
-}
-
-hipError_t launch_eig_backward(const double *T, const double *Q, int n, int batch, const double *wr,
-                               const double *wi, const double *gwr, const double *gwi, double *dH, int hess_mask,
-                               hipStream_t s)
-{
-    (void)T; (void)Q; (void)n; (void)batch; (void)wr; (void)wi; (void)gwr; (void)gwi; (void)dH;
-    (void)hess_mask; (void)s;
-    return hipErrorNotSupported;
 }
 
 } // namespace hqr

@@ -42,7 +42,7 @@ def test_argument_validation_without_device_work(L):
     assert L.hqr_schur(p, None, 2, 2, p, None, None) == -6
     assert L.hqr_schur(p, None, 0, 1, p, p, None) == 0
     assert L.hqr_schur_batched(p, None, p, p, -1, p, p, p, p, None) == -5
-    assert L.hqr_eig_backward_batched(p, p, 500, 1, p, p, p, p, p, 1, None) == -3
+    assert L.hqr_eig_backward_batched(p, p, -2, 1, p, p, p, p, p, 1, None) == -3
 
 
 def test_params_roundtrip_and_rejection(L):

@@ -101,6 +101,28 @@ def test_big_aed_window(gpu):
     assert_schur(H, T, Q, w, tag="bigaed600")
 
 
+@pytest.mark.parametrize("nsmall", [8, 16])
+@pytest.mark.parametrize("n,params", [(90, {}), (300, {"ns": 16, "nw": 80})])
+def test_multishift_small_solver(gpu, n, params, nsmall):
+    _say(f"case multishift small solver n={n} small_shifts={nsmall} params={params}")
+    H = hi.hessrand(n, seed=70 + n)
+    p = dict(params)
+    p["small_shifts"] = nsmall
+    T, Q, w, info, st = run_gpu(H, p)
+    _say(f"stats {st}")
+    assert info == 0
+    assert_schur(H, T, Q, w, tag=f"ms{nsmall}_{n}")
+
+
+def test_single_stream_matches_two_streams(gpu):
+    _say("case streams=1 vs streams=2 (bitwise identical: same kernels, same order per element)")
+    H = hi.hessrand(350, seed=3)
+    T1, Q1, w1, i1, _ = run_gpu(H, {"ns": 16, "nw": 64, "streams": 1})
+    T2, Q2, w2, i2, _ = run_gpu(H, {"ns": 16, "nw": 64, "streams": 2})
+    assert i1 == 0 and i2 == 0
+    assert np.array_equal(T1, T2) and np.array_equal(Q1, Q2)
+
+
 def test_syn_matrix(gpu):
     _say("case syn_n n=320")
     H, ev = hi.syn_matrix(320, seed=5)

@@ -372,6 +372,68 @@ def test_aed_preserves_spectrum_and_hessenberg_form():
         assert d.max() <= 1e-10 * np.linalg.norm(H)
 
 
+# ---------------------------------------------------------------- gradient
+
+def loss_and_cotangent(w):
+    """L = sum softplus(Re l) + 0.1 |l|^2 and g = dL/dRe + i dL/dIm."""
+    re = w.real
+    L = np.sum(np.logaddexp(0.0, re)) + 0.1 * np.sum(np.abs(w) ** 2)
+    g = 1.0 / (1.0 + np.exp(-re)) + 0.2 * w
+    return L, g
+
+
+def loss_of(H):
+    T, Q, w, info, _ = oracle.schur(H, want_q=False)
+    assert info == 0
+    return loss_and_cotangent(w)[0]
+
+
+def hess_direction(n, g):
+    D = np.triu(g.standard_normal((n, n)), -1)
+    return D / np.linalg.norm(D)
+
+
+def test_gradient_of_trace_is_identity():
+    H = hi.hessrand(30, seed=50)
+    T, Q, w, info, _ = oracle.schur(H)
+    dH = oracle.eig_backward(T, Q, w, np.ones(30))
+    assert np.abs(dH - np.eye(30)).max() <= 1e-10
+
+
+def test_gradient_of_trace_square():
+    H = hi.hessrand(25, seed=51)
+    T, Q, w, info, _ = oracle.schur(H)
+    dH = oracle.eig_backward(T, Q, w, 2.0 * np.conj(w))
+    ref = np.triu(2.0 * H.T, -1)
+    assert np.abs(dH - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+def test_gradient_normal_sum_abs_square():
+    H, ev = hi.prescribed_hessenberg(40, seed=52, separated=True)
+    T, Q, w, info, _ = oracle.schur(H)
+    dH = oracle.eig_backward(T, Q, w, 2.0 * w, hess_mask=False)
+    assert np.abs(dH - 2.0 * H).max() <= 1e-9 * np.abs(H).max()
+
+
+@pytest.mark.parametrize("kind", ["normal", "nonnormal"])
+def test_gradient_central_differences(kind):
+    n = 24
+    if kind == "normal":
+        H, _ = hi.prescribed_hessenberg(n, seed=53, separated=True)
+    else:
+        H, _ = hi.syn_matrix(n, seed=54)
+    T, Q, w, info, _ = oracle.schur(H)
+    _, g = loss_and_cotangent(w)
+    dH = oracle.eig_backward(T, Q, w, g)
+    gen = np.random.default_rng(55)
+    h = 1e-6
+    for _ in range(6):
+        D = hess_direction(n, gen)
+        fd = (loss_of(H + h * D) - loss_of(H - h * D)) / (2 * h)
+        an = np.sum(dH * D)
+        assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (fd, an)
+
+
 # -------------------------------------------------------------- mutations
 
 def _catch(fn):
@@ -389,6 +451,7 @@ MUTATION_PINS = {
     4: lambda: test_swap_matches_lapack_dtrexc(1, 1),
     5: lambda: test_schur_n2_closed_form(CASES_2x2[1]),
     6: lambda: test_prescribed_normal_spectrum(256),
+    7: lambda: test_gradient_central_differences("nonnormal"),
     8: lambda: test_against_lapack_eigenvalues(300, "hessrand"),
 }
 
