@@ -66,7 +66,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=2048)
     ap.add_argument("--streams", type=int, default=2)
+    ap.add_argument("--small-shifts", type=int, default=0)
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="only run 5 plain device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calib:
+        import torch
+        nel = args.copy_calib // 8
+        a = torch.ones(nel, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes": nel * 8, "copies": 5}))
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
@@ -82,7 +95,7 @@ def main():
     dev = torch.device("cuda:0")
     H0 = make_input(spec, args.seed)
     H0d = torch.from_numpy(np.ascontiguousarray(H0.T)).to(dev)  # row-major of H^T = column-major H
-    params = {"ns": spec["ns"], "nw": spec["nw"], "streams": args.streams}
+    params = {"ns": spec["ns"], "nw": spec["nw"], "streams": args.streams, "small_shifts": args.small_shifts}
     nsteps = args.warmup + args.steps
     # stage one input copy per step so the timed region is solves only
     Hs = [H0d.clone() for _ in range(nsteps)]
@@ -106,6 +119,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = profiling.read()
+    lds_split = profiling.lds_split()
     profiling.enable(False)
     stats = hq.last_stats()
     dt = (t1 - t0) / args.steps
@@ -131,13 +145,15 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "ns": spec["ns"], "nw": spec["nw"],
-                   "want_q": True, "seed": args.seed},
+                   "want_q": True, "seed": args.seed, "streams": args.streams,
+                   "small_shifts": args.small_shifts or 2},
         "solves_per_s": 1.0 / dt,
         "accuracy": {"backward_rel": be, "backward_u": be / u, "orth": orth, "bound_100nu": 100 * n * u},
         "run_stats": stats,
     }
     out["roofline"] = profiling.roofline(prof, args.steps)
     out["kernel_times"] = profiling.summary(prof, args.steps)
+    out["kernel_times"]["lds_iteration"]["split"] = lds_split
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.seed, args.cpu_n)
     else:

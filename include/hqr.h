@@ -116,6 +116,10 @@ int hqr_last_stats(int64_t *stats, int len);
 int hqr_profile_enable(int on);
 int hqr_profile_reset(void);
 int hqr_profile_read(double *ms, int64_t *launches, double *flops, double *bytes, int nclass);
+/* Device wall-clock ticks spent inside the one-workgroup LDS iteration kernel,
+ * split into Schur solve, reordering (spike test and swaps), Hessenberg
+ * restoration and total, summed over the profiled launches. */
+int hqr_profile_ticks(int64_t *ticks, int len);
 
 /* Free per-device workspace and helper streams. */
 int hqr_finalize(void);

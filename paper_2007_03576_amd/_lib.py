@@ -24,7 +24,7 @@ class HqrParams(ctypes.Structure):
 
 EXPORTS = ["hqr_set_params", "hqr_get_params", "hqr_schur", "hqr_schur_ex", "hqr_schur_batched",
            "hqr_eig_backward_batched", "hqr_last_stats", "hqr_finalize", "hqr_profile_enable",
-           "hqr_profile_reset", "hqr_profile_read"]
+           "hqr_profile_reset", "hqr_profile_read", "hqr_profile_ticks"]
 
 
 class HqrError(RuntimeError):
@@ -53,6 +53,7 @@ def lib():
     L.hqr_profile_reset.argtypes = []
     dp = ctypes.POINTER(ctypes.c_double)
     L.hqr_profile_read.argtypes = [dp, ctypes.POINTER(ctypes.c_int64), dp, dp, ctypes.c_int]
+    L.hqr_profile_ticks.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_int
     _lib = L

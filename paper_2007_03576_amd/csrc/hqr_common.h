@@ -29,7 +29,9 @@ struct IterStatus {
     int info;    // 0, or >0 when the small solver did not converge
     int changed; // 1 when H was modified and the factor must be propagated
     int pad;
-    double beta; // new subdiagonal entry left of an AED window after restoration
+    double beta; // new subdiagonal entry left of a large AED window after restoration;
+                 // for the LDS iteration kernel: its algorithmic flop count
+    long long tick[4]; // LDS iteration kernel: wall-clock ticks of Schur solve, reordering, restoration, total
     double cr[MAXCAND];
     double ci[MAXCAND];
 };

@@ -109,6 +109,7 @@ std::vector<ProfRec> g_prof;
 std::vector<hipEvent_t> g_prof_pool;
 double g_prof_ms[NCLASS], g_prof_flops[NCLASS], g_prof_bytes[NCLASS];
 int64_t g_prof_n[NCLASS];
+long long g_prof_ticks[4]; // LDS iteration: Schur, reordering, restoration, total (device wall clock)
 
 hipEvent_t prof_event()
 {
@@ -143,6 +144,20 @@ void prof_end(int id, hipStream_t s, double flops, double bytes)
     hipEventRecord(g_prof[id].b, s);
     g_prof[id].flops = flops;
     g_prof[id].bytes = bytes;
+}
+
+void prof_set_flops(int id, double flops)
+{
+    if (id < 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof[id].flops = flops;
+}
+
+void prof_add_ticks(const long long *t)
+{
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (int i = 0; i < 4; ++i) g_prof_ticks[i] += t[i];
 }
 
 // fold finished records into the per-class totals
@@ -209,18 +224,23 @@ int take_slot(Ctx &C)
     Workspace &W = *C.W;
     int s = W.slot_next;
     W.slot_next = (W.slot_next + 1) % W.nslots;
-    if (C.two && W.slot_used[s]) {
+    // the deferred stream may still read this slot (from any recursion level)
+    if (W.slot_used[s]) {
         hipStreamWaitEvent(C.hi, W.slot_ev[s], 0);
+        W.slot_used[s] = 0;
     }
-    W.slot_used[s] = 1;
     return s;
 }
 
 double *slot_ptr(Workspace &W, int s) { return W.ubuf + (size_t)s * slot_ustride(); }
 
+// Marks the slot as read by deferred work enqueued so far on the second stream.
 void release_slot(Ctx &C, int s)
 {
-    if (C.two) hipEventRecord(C.W->slot_ev[s], C.W->lo);
+    if (C.two) {
+        hipEventRecord(C.W->slot_ev[s], C.W->lo);
+        C.W->slot_used[s] = 1;
+    }
 }
 
 int ensure_depth(Workspace &W, int depth, int w)
@@ -458,7 +478,7 @@ int sweep(Ctx &C, const View &V, int ktop, int kbot, int nsh, const double *sr, 
                 // direct-reflector flops inside the window: about 11 per touched
                 // entry, 3 rows + 3 columns of A and 3 columns of U per reflector
                 double wa = R.w[i].wa;
-                fl += 11.0 * 3.0 * (2.0 * wa) * R.w[i].nb * R.w[i].nsteps;
+                fl += 12.0 * (2.0 * wa + 5.0) * R.w[i].nb * R.w[i].nsteps;
                 by += 2.0 * 8.0 * wa * wa + 8.0 * wa * wa;
             }
             prof_end(pid, C.hi, fl, by);
@@ -545,8 +565,7 @@ int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd
     }
     int wd = std::min(w, MMAX);
     int slc = take_slot(C);
-    double *Utc = slot_ptr(W, slc);
-    release_slot(C, slc);
+    double *Utc = slot_ptr(W, slc); // used on the critical stream only
     int pidc = prof_begin(3, C.hi);
     CK(launch_corner_deflate(T, w, w, wd, Vw, w, s, C.smlnum, Utc, W.st_dev, C.hi));
     prof_end(pidc, C.hi, 0.0, 0.0);
@@ -622,6 +641,8 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
             prof_end(pid, C.hi, 0.0, 0.0);
             if (C.stats) C.stats[6]++;
             if (read_status(C, nwp)) return -1;
+            prof_set_flops(pid, S.beta);
+            prof_add_ticks(S.tick);
             ktop = S.ktop;
             if (S.kind == 0) {
                 if (S.info > 0) {
@@ -659,6 +680,8 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
                 CK(launch_iter(V.H, V.ld, V.n, ilo, kbot, wv, P.nmin, C.smlnum, P.itmax, Ut, W.st_dev, C.hi, P.nsmall));
                 prof_end(pid, C.hi, 0.0, 0.0);
                 if (read_status(C, MMAX)) return -1;
+                prof_set_flops(pid, S.beta);
+                prof_add_ticks(S.tick);
                 if (S.kind == 0) {
                     if (S.info > 0) {
                         *info_out = S.info;
@@ -914,7 +937,16 @@ int hqr_profile_reset(void)
         g_prof_ms[c] = g_prof_flops[c] = g_prof_bytes[c] = 0.0;
         g_prof_n[c] = 0;
     }
+    for (int i = 0; i < 4; ++i) g_prof_ticks[i] = 0;
     return 0;
+}
+
+int hqr_profile_ticks(int64_t *ticks, int len)
+{
+    if (!ticks || len <= 0) return -1;
+    int m = std::min(len, 4);
+    for (int i = 0; i < m; ++i) ticks[i] = g_prof_ticks[i];
+    return m;
 }
 
 int hqr_profile_read(double *ms, int64_t *launches, double *flops, double *bytes, int nclass)

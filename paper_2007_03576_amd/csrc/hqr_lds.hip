@@ -37,6 +37,7 @@ struct SmemCore {
     double sc[8];
     int ic[8];
     double shb[16 * 16]; // trailing block whose eigenvalues become the shifts of a multishift sweep
+    double flops;        // algorithmic flops of the reflector applications (thread 0 counts)
 };
 
 // LDS-resident matrix and accumulated factor for orders <= MMAX.
@@ -193,93 +194,264 @@ __device__ inline double block_max(SmemCore &S, double v)
     return t;
 }
 
-// Chase nb bulges through the matrix held in LDS.  Indices are global; local
-// index = global - off.  Active block [ktop,kbot].  Bulge b is at position
-// p0 + t - 3b at step t and acts when ktop-1 <= k <= kend (a reflector at k
-// acts on rows/cols k+1..k+3).  Left application: local columns up to colhi.
-// Right application: local rows 0..min(k+4,kbot).  Z (nz rows) accumulates.
+// Reflector of one bulge at position k (acting on k+1..k+m, local kl = k - off):
+// from the shift polynomial when the bulge is introduced (k = ktop-1), else
+// from the bulge column.
+__device__ inline void bulge_reflector(const SmemCore &S, const double *A, int lda, int off, int ktop, int kbot,
+                                       int b, int k, int &m, double &v1, double &v2, double &tau, double &beta)
+{
+    m = min(3, kbot - k);
+    const int kl = k - off;
+    double x0, x1, x2;
+    if (k == ktop - 1) {
+        shift_column(A, lda, kl + 1, kbot - off, S.sr[2 * b], S.si[2 * b], S.sr[2 * b + 1], S.si[2 * b + 1], x0, x1,
+                     x2);
+    } else {
+        x0 = A[(kl + 1) + kl * lda];
+        x1 = A[(kl + 2) + kl * lda];
+        x2 = (m == 3) ? A[(kl + 3) + kl * lda] : 0.0;
+    }
+    house3(m, x0, x1, x2, v1, v2, tau, beta);
+    if (m < 3) v2 = 0.0;
+}
+
+// y <- P y for an m-vector (m = 2 or 3), P = I - tau v v^T, v = (1, v1, v2).
+__device__ inline void refl3(int m, double tau, double v1, double v2, double &y0, double &y1, double &y2)
+{
+    double s = tau * (y0 + v1 * y1 + (m == 3 ? v2 * y2 : 0.0));
+    y0 -= s;
+    y1 -= s * v1;
+    if (m == 3) y2 -= s * v2;
+}
+
+// Chase nb bulges through the matrix held in LDS (or global memory).  Indices
+// are global; local index = global - off.  Active block [ktop,kbot].  Bulge b
+// is at position p0 + t - 3b at step t and acts when ktop-1 <= k <= kend (a
+// reflector at k acts on rows/columns k+1..k+3).  Left application: local
+// columns up to colhi; right application: local rows 0..min(k+4,kbot); Z (nz
+// rows) accumulates.
+//
+// One step applies the reflectors of all active bulges in a single barrier
+// phase.  The regions they touch are split so that no element is written by
+// two threads: each bulge's own m x m block (P^T B P), the cross blocks between
+// the rows of a higher bulge and the columns of a lower one (P_hi^T X P_lo),
+// the left products right of the lowest active block, the right products
+// above the highest active block plus each bulge's row k+4, and Z.  For a
+// single bulge every thread computes the reflector itself (no barrier before
+// the products) and the bulge column is written one step later, when no
+// thread reads it any more.
 __device__ void chain_chase(SmemCore &S, double *A, int lda, int off, int ktop, int kbot, int p0, int nsteps,
                             int kend, int nb, int colhi, double *Z, int ldz, int nz)
 {
     const int tid = threadIdx.x;
-    const int tpb = NT / nb; // threads per bulge in the apply phases
-    const int myb = tid / tpb, mys = tid - myb * tpb;
+    const int kbl = kbot - off;
+    // pending bulge-column write for the single-bulge path (thread 0)
+    int pend_kl = -1, pend_m = 0;
+    double pend_beta = 0.0;
+    double fl = 0.0;
     for (int t = 0; t < nsteps; ++t) {
-        if (tid < nb) {
-            int b = tid;
-            int k = p0 + t - 3 * b;
-            int m = 0;
+        int blo = nb, bhi = -1;
+        double r_v1 = 0.0, r_v2 = 0.0, r_tau = 0.0, r_beta = 0.0;
+        int r_m = 0, r_kl = 0;
+        if (nb == 1) {
+            int k = p0 + t;
             if (k >= ktop - 1 && k <= kend) {
-                m = min(3, kbot - k);
-                int kl = k - off;
-                double x0, x1, x2;
-                if (k == ktop - 1) {
-                    shift_column(A, lda, kl + 1, kbot - off, S.sr[2 * b], S.si[2 * b], S.sr[2 * b + 1],
-                                 S.si[2 * b + 1], x0, x1, x2);
-                } else {
-                    x0 = A[(kl + 1) + kl * lda];
-                    x1 = A[(kl + 2) + kl * lda];
-                    x2 = (m == 3) ? A[(kl + 3) + kl * lda] : 0.0;
-                }
-                double v1, v2, tau, beta;
-                house3(m, x0, x1, x2, v1, v2, tau, beta);
-                if (k >= ktop) {
-                    A[(kl + 1) + kl * lda] = beta;
-                    A[(kl + 2) + kl * lda] = 0.0;
-                    if (m == 3) A[(kl + 3) + kl * lda] = 0.0;
-                }
-                S.bk[b] = kl;
-                S.bv1[b] = v1;
-                S.bv2[b] = (m == 3) ? v2 : 0.0;
-                S.btau[b] = tau;
-                S.bc0[b] = kl + 1;
+                bulge_reflector(S, A, lda, off, ktop, kbot, 0, k, r_m, r_v1, r_v2, r_tau, r_beta);
+                r_kl = k - off;
+                blo = bhi = 0;
+                // the introduction reads the leading block, which the products overwrite
+                if (k == ktop - 1) __syncthreads();
             }
-            S.bm[b] = m;
+        } else {
+            if (tid < nb) {
+                int b = tid;
+                int k = p0 + t - 3 * b;
+                int m = 0;
+                if (k >= ktop - 1 && k <= kend) {
+                    double v1, v2, tau, beta;
+                    bulge_reflector(S, A, lda, off, ktop, kbot, b, k, m, v1, v2, tau, beta);
+                    const int kl = k - off;
+                    if (k >= ktop) {
+                        A[(kl + 1) + kl * lda] = beta;
+                        A[(kl + 2) + kl * lda] = 0.0;
+                        if (m == 3) A[(kl + 3) + kl * lda] = 0.0;
+                    }
+                    S.bk[b] = kl;
+                    S.bv1[b] = v1;
+                    S.bv2[b] = v2;
+                    S.btau[b] = tau;
+                }
+                S.bm[b] = m;
+            }
+            __syncthreads();
+            for (int b = 0; b < nb; ++b)
+                if (S.bm[b] != 0) {
+                    blo = min(blo, b);
+                    bhi = max(bhi, b);
+                }
         }
-        __syncthreads();
-        // left: rows kl+1..kl+m, columns bc0..colhi (tpb threads per bulge)
-        if (myb < nb && S.bm[myb] != 0 && S.btau[myb] != 0.0) {
-            const int m = S.bm[myb];
-            const int r = S.bk[myb] + 1;
-            const double tau = S.btau[myb], v1 = S.bv1[myb], v2 = S.bv2[myb];
-            for (int c = S.bc0[myb] + mys; c <= colhi; c += tpb) {
+        if (bhi < 0) {
+            if (nb > 1) __syncthreads();
+            continue;
+        }
+        // geometry of this step (uniform across threads)
+        auto KL = [&](int b) { return nb == 1 ? r_kl : S.bk[b]; };
+        auto M = [&](int b) { return nb == 1 ? r_m : S.bm[b]; };
+        auto TAU = [&](int b) { return nb == 1 ? r_tau : S.btau[b]; };
+        auto V1 = [&](int b) { return nb == 1 ? r_v1 : S.bv1[b]; };
+        auto V2 = [&](int b) { return nb == 1 ? r_v2 : S.bv2[b]; };
+        const int nact = bhi - blo + 1;
+        const int klo = KL(blo), mlo = M(blo);
+        const int khi = KL(bhi);
+        const int c0L = klo + mlo + 1;             // free left columns: c0L..colhi
+        const int ncL = max(0, colhi - c0L + 1);
+        const int nrR = max(0, khi + 1);           // free right rows: 0..khi
+        const int perR = nrR + nz + 1;             // + Z rows + row k+4
+        const int npairs = nact * (nact - 1) / 2;
+        const int nL = nact * ncL, nR = nact * perR;
+        const int total = nL + nR + nact + npairs;
+        if (tid == 0) fl += 4.0 * 3.0 * (double)(nL + nR) + 40.0 * (nact + npairs);
+        for (int it = tid; it < total; it += NT) {
+            if (it < nL) {
+                const int b = blo + it / ncL, c = c0L + it % ncL;
+                const int m = M(b), r = KL(b) + 1;
+                const double tau = TAU(b);
+                if (tau == 0.0) continue;
                 double *col = A + c * lda + r;
-                double a0 = col[0], a1 = col[1];
-                double a2 = (m == 3) ? col[2] : 0.0;
-                double s = tau * (a0 + v1 * a1 + v2 * a2);
-                col[0] = a0 - s;
-                col[1] = a1 - s * v1;
-                if (m == 3) col[2] = a2 - s * v2;
+                double y0 = col[0], y1 = col[1], y2 = (m == 3) ? col[2] : 0.0;
+                refl3(m, tau, V1(b), V2(b), y0, y1, y2);
+                col[0] = y0;
+                col[1] = y1;
+                if (m == 3) col[2] = y2;
+            } else if (it < nL + nR) {
+                const int q = it - nL;
+                const int b = blo + q / perR, r = q % perR;
+                const int m = M(b), kl = KL(b);
+                const double tau = TAU(b);
+                if (tau == 0.0) continue;
+                double *Mx;
+                int ld;
+                if (r < nrR) {
+                    Mx = A + r;
+                    ld = lda;
+                } else if (r < nrR + nz) {
+                    Mx = Z + (r - nrR);
+                    ld = ldz;
+                } else {
+                    if (m != 3 || kl + 4 > kbl) continue;
+                    Mx = A + (kl + 4);
+                    ld = lda;
+                }
+                double y0 = Mx[(kl + 1) * ld], y1 = Mx[(kl + 2) * ld], y2 = (m == 3) ? Mx[(kl + 3) * ld] : 0.0;
+                refl3(m, tau, V1(b), V2(b), y0, y1, y2);
+                Mx[(kl + 1) * ld] = y0;
+                Mx[(kl + 2) * ld] = y1;
+                if (m == 3) Mx[(kl + 3) * ld] = y2;
+            } else if (it < nL + nR + nact) {
+                // own block: B <- P^T B P on rows/columns kl+1..kl+m (m = 2 is the 3x3
+                // case with v2 = 0 and the third row/column left out)
+                const int b = blo + (it - nL - nR);
+                const int m = M(b), kl = KL(b);
+                const double tau = TAU(b), v1 = V1(b), v2 = V2(b);
+                if (tau == 0.0) continue;
+                double B00, B01, B02, B10, B11, B12, B20 = 0.0, B21 = 0.0, B22 = 0.0;
+                double *a = A + (kl + 1) + (kl + 1) * lda;
+                B00 = a[0];
+                B10 = a[1];
+                B01 = a[lda];
+                B11 = a[1 + lda];
+                B02 = (m == 3) ? a[2 * lda] : 0.0;
+                B12 = (m == 3) ? a[1 + 2 * lda] : 0.0;
+                if (m == 3) {
+                    B20 = a[2];
+                    B21 = a[2 + lda];
+                    B22 = a[2 + 2 * lda];
+                }
+                refl3(3, tau, v1, v2, B00, B10, B20);
+                refl3(3, tau, v1, v2, B01, B11, B21);
+                refl3(3, tau, v1, v2, B02, B12, B22);
+                refl3(3, tau, v1, v2, B00, B01, B02);
+                refl3(3, tau, v1, v2, B10, B11, B12);
+                refl3(3, tau, v1, v2, B20, B21, B22);
+                a[0] = B00;
+                a[1] = B10;
+                a[lda] = B01;
+                a[1 + lda] = B11;
+                if (m == 3) {
+                    a[2] = B20;
+                    a[2 + lda] = B21;
+                    a[2 * lda] = B02;
+                    a[1 + 2 * lda] = B12;
+                    a[2 + 2 * lda] = B22;
+                }
+            } else if (it < nL + nR + nact + npairs) {
+                // cross block: rows of bulge bu (higher) x columns of bulge bd (lower)
+                int p = it - nL - nR - nact;
+                int i = 0;
+                while (p >= nact - 1 - i) {
+                    p -= nact - 1 - i;
+                    ++i;
+                }
+                const int bd = blo + i, bu = blo + i + 1 + p;
+                const int mu = M(bu), md = M(bd), ku = KL(bu), kd = KL(bd);
+                const double tu = TAU(bu), td = TAU(bd);
+                const double u1 = V1(bu), u2 = V2(bu), d1 = V1(bd), d2 = V2(bd);
+                double *x = A + (ku + 1) + (kd + 1) * lda;
+                double X00 = x[0], X10 = x[1], X20 = (mu == 3) ? x[2] : 0.0;
+                double X01 = x[lda], X11 = x[1 + lda], X21 = (mu == 3) ? x[2 + lda] : 0.0;
+                double X02 = 0.0, X12 = 0.0, X22 = 0.0;
+                if (md == 3) {
+                    X02 = x[2 * lda];
+                    X12 = x[1 + 2 * lda];
+                    X22 = (mu == 3) ? x[2 + 2 * lda] : 0.0;
+                }
+                if (tu != 0.0) {
+                    refl3(3, tu, u1, u2, X00, X10, X20);
+                    refl3(3, tu, u1, u2, X01, X11, X21);
+                    refl3(3, tu, u1, u2, X02, X12, X22);
+                }
+                if (td != 0.0) {
+                    refl3(3, td, d1, d2, X00, X01, X02);
+                    refl3(3, td, d1, d2, X10, X11, X12);
+                    refl3(3, td, d1, d2, X20, X21, X22);
+                }
+                x[0] = X00;
+                x[1] = X10;
+                x[lda] = X01;
+                x[1 + lda] = X11;
+                if (mu == 3) {
+                    x[2] = X20;
+                    x[2 + lda] = X21;
+                }
+                if (md == 3) {
+                    x[2 * lda] = X02;
+                    x[1 + 2 * lda] = X12;
+                    if (mu == 3) x[2 + 2 * lda] = X22;
+                }
             }
         }
-        __syncthreads();
-        // right: columns kl+1..kl+m over rows 0..min(kl+4, kbot-off) of A and all rows of Z
-        if (myb < nb && S.bm[myb] != 0 && S.btau[myb] != 0.0) {
-            const int m = S.bm[myb];
-            const int kl = S.bk[myb];
-            const double tau = S.btau[myb], v1 = S.bv1[myb], v2 = S.bv2[myb];
-            const int rmax = min(kl + 4, kbot - off);
-            const int total = rmax + 1 + nz;
-            for (int r = mys; r < total; r += tpb) {
-                double *M;
-                int ld;
-                if (r <= rmax) {
-                    M = A + r;
-                    ld = lda;
-                } else {
-                    M = Z + (r - rmax - 1);
-                    ld = ldz;
-                }
-                double a0 = M[(kl + 1) * ld], a1 = M[(kl + 2) * ld];
-                double a2 = (m == 3) ? M[(kl + 3) * ld] : 0.0;
-                double s = tau * (a0 + v1 * a1 + v2 * a2);
-                M[(kl + 1) * ld] = a0 - s;
-                M[(kl + 2) * ld] = a1 - s * v1;
-                if (m == 3) M[(kl + 3) * ld] = a2 - s * v2;
+        if (nb == 1 && tid == 0) {
+            // single bulge: write the previous step's bulge column (nobody reads it now)
+            if (pend_m > 0) {
+                A[(pend_kl + 1) + pend_kl * lda] = pend_beta;
+                A[(pend_kl + 2) + pend_kl * lda] = 0.0;
+                if (pend_m == 3) A[(pend_kl + 3) + pend_kl * lda] = 0.0;
             }
+            pend_m = (r_kl + off >= ktop) ? r_m : 0;
+            pend_kl = r_kl;
+            pend_beta = r_beta;
         }
         __syncthreads();
     }
+    if (nb == 1) {
+        if (tid == 0 && pend_m > 0) {
+            A[(pend_kl + 1) + pend_kl * lda] = pend_beta;
+            A[(pend_kl + 2) + pend_kl * lda] = 0.0;
+            if (pend_m == 3) A[(pend_kl + 3) + pend_kl * lda] = 0.0;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) S.flops += fl;
 }
 
 // Largest l in (lo,hi] whose subdiagonal A[l,l-1] is zero or negligible
@@ -573,142 +745,289 @@ __device__ void solve_small(int q, double *K, double *r, double *y, double smin)
     for (int k = 0; k < q; ++k) y[pc[k]] = z[k];
 }
 
-// One thread: orthogonal G (m x m, column major, m = p+q) exchanging the
-// blocks of D = T(j:j+m, j:j+m); Dn = G^T D G with the (2,1) block zeroed.
-// Returns false when the exchange fails the stability tests.
-__device__ bool swap_transform(const double *T, int ldt, int j, int p, int q, double smlnum, double *G,
-                               double *Dn)
+// Standardizing rotation of a 2x2 block held in registers: returns the total
+// rotation (cs, sn) and leaves the standardized values in (a, b, c, d).
+__device__ inline void std2_regs(double &a, double &b, double &c, double &d, double &cst, double &snt)
 {
-    int m = p + q;
-    double D[16];
-    double dnorm = 0.0;
-    for (int c = 0; c < m; ++c)
-        for (int r = 0; r < m; ++r) {
-            D[r + 4 * c] = T[(j + r) + (j + c) * ldt];
-            dnorm = fmax(dnorm, fabs(D[r + 4 * c]));
+    cst = 1.0;
+    snt = 0.0;
+    for (int pass = 0; pass < 3; ++pass) {
+        double cs, sn;
+        int mode = std_rot(a, b, c, d, cs, sn);
+        if (mode == 0) break;
+        double m00 = a * cs + b * sn, m01 = -a * sn + b * cs;
+        double m10 = c * cs + d * sn, m11 = -c * sn + d * cs;
+        a = cs * m00 + sn * m10;
+        b = cs * m01 + sn * m11;
+        c = -sn * m00 + cs * m10;
+        d = -sn * m01 + cs * m11;
+        double t = cst * cs - snt * sn;
+        snt = snt * cs + cst * sn;
+        cst = t;
+        if (mode == 1) {
+            c = 0.0;
+            break;
         }
-    if (p == 1 && q == 1) {
-        double t11 = D[0], t12 = D[4], t22 = D[5];
-        double rr = hypot(t12, t22 - t11);
-        double cs = 1.0, sn = 0.0;
-        if (rr != 0.0) {
-            cs = t12 / rr;
-            sn = (t22 - t11) / rr;
-        }
-        G[0] = cs; G[1] = sn; G[2] = -sn; G[3] = cs;
-        // Dn = G^T D G, then exact diagonal and zero (2,1)
-        double b01 = cs * (cs * t12 + sn * t22) - sn * (cs * t11 * 0.0 + 0.0) ; // placeholder overwritten below
-        (void)b01;
-        double m00 = cs * t11, m01 = -sn * t11 + cs * t12;
-        double m10 = sn * t22, m11 = cs * t22; // rows of D G: [t11 t12;0 t22] G
-        // D G = [[t11*cs + t12*sn, -t11*sn + t12*cs], [t22*sn, t22*cs]]
-        m00 = t11 * cs + t12 * sn;
-        m01 = -t11 * sn + t12 * cs;
-        m10 = t22 * sn;
-        m11 = t22 * cs;
-        // G^T (D G)
-        double n01 = cs * m01 + sn * m11;
-        (void)m00;
-        (void)m10;
-        Dn[0] = t22; Dn[4] = n01; Dn[1] = 0.0; Dn[5] = t11;
-        return true;
+        double avg = 0.5 * (a + d);
+        a = d = avg;
+        if (b * c < 0.0) break;
     }
-    double thresh = fmax(10.0 * kU * dnorm, smlnum);
-    int pq = p * q;
-    double K[16], rhs[4], X[4];
+}
+
+// One thread: orthogonal G exchanging the blocks of D = T(j:j+M, j:j+M)
+// (top block P x P, bottom block Q x Q; at least one of them 2x2), with the
+// two new diagonal blocks standardized.  Dn = G^T D G with the (2,1) block
+// exactly zero.  Bai-Demmel: solve A11 X - X A22 = A12, QR of [-X; I_Q],
+// weak (new (2,1) block) and strong (reconstruction) stability tests.
+// Sizes are compile-time so every array stays in registers; pivot choices
+// are applied through unrolled selects.
+template <int P, int Q>
+__device__ bool swap_xform(const double *T, int ldt, int j, double smlnum, double *Gout, double *Dout)
+{
+    constexpr int M = P + Q, PQ = P * Q;
+    double D[M][M];
+    double dnorm = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            D[r][c] = T[(j + r) + (j + c) * ldt];
+            dnorm = fmax(dnorm, fabs(D[r][c]));
+        }
+    const double thresh = fmax(10.0 * kU * dnorm, smlnum);
+    // Kronecker form of the Sylvester equation: unknown x[r + P c] = X[r][c]
+    double K[PQ][PQ], rhs[PQ];
     double kmax = 0.0;
-    for (int i = 0; i < 16; ++i) K[i] = 0.0;
-    for (int c = 0; c < q; ++c)
-        for (int r = 0; r < p; ++r) {
-            int row = r + p * c;
-            rhs[row] = D[r + 4 * (p + c)];
-            for (int c2 = 0; c2 < q; ++c2)
-                for (int r2 = 0; r2 < p; ++r2) {
-                    int col = r2 + p * c2;
+#pragma unroll
+    for (int c = 0; c < Q; ++c)
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const int row = r + P * c;
+            rhs[row] = D[r][P + c];
+#pragma unroll
+            for (int c2 = 0; c2 < Q; ++c2)
+#pragma unroll
+                for (int r2 = 0; r2 < P; ++r2) {
                     double v = 0.0;
-                    if (c == c2) v += D[r + 4 * r2];
-                    if (r == r2) v -= D[(p + c2) + 4 * (p + c)];
-                    K[row * 4 + col] = v;
+                    if (c == c2) v += D[r][r2];
+                    if (r == r2) v -= D[P + c2][P + c];
+                    K[row][r2 + P * c2] = v;
                     kmax = fmax(kmax, fabs(v));
                 }
         }
-    solve_small(pq, K, rhs, X, fmax(kU * kmax, smlnum));
-    // QR of M = [-X; I_q] by q reflectors; G accumulates the reflectors
-    double M[16];
-    for (int i = 0; i < 16; ++i) {
-        M[i] = 0.0;
-        G[i] = 0.0;
+    const double smin = fmax(kU * kmax, smlnum);
+    int perm[PQ];
+#pragma unroll
+    for (int i = 0; i < PQ; ++i) perm[i] = i;
+#pragma unroll
+    for (int k = 0; k < PQ; ++k) {
+        int br = k, bc = k;
+        double best = -1.0;
+#pragma unroll
+        for (int i = k; i < PQ; ++i)
+#pragma unroll
+            for (int c2 = k; c2 < PQ; ++c2)
+                if (fabs(K[i][c2]) > best) {
+                    best = fabs(K[i][c2]);
+                    br = i;
+                    bc = c2;
+                }
+#pragma unroll
+        for (int i = k + 1; i < PQ; ++i)
+            if (br == i) {
+#pragma unroll
+                for (int c2 = 0; c2 < PQ; ++c2) {
+                    double t = K[k][c2];
+                    K[k][c2] = K[i][c2];
+                    K[i][c2] = t;
+                }
+                double t = rhs[k];
+                rhs[k] = rhs[i];
+                rhs[i] = t;
+            }
+#pragma unroll
+        for (int c2 = k + 1; c2 < PQ; ++c2)
+            if (bc == c2) {
+#pragma unroll
+                for (int i = 0; i < PQ; ++i) {
+                    double t = K[i][k];
+                    K[i][k] = K[i][c2];
+                    K[i][c2] = t;
+                }
+                int t = perm[k];
+                perm[k] = perm[c2];
+                perm[c2] = t;
+            }
+        if (fabs(K[k][k]) < smin) K[k][k] = (K[k][k] >= 0.0) ? smin : -smin;
+#pragma unroll
+        for (int i = k + 1; i < PQ; ++i) {
+            const double f = K[i][k] / K[k][k];
+#pragma unroll
+            for (int c2 = k; c2 < PQ; ++c2) K[i][c2] -= f * K[k][c2];
+            rhs[i] -= f * rhs[k];
+        }
     }
-    for (int c = 0; c < q; ++c) {
-        for (int r = 0; r < p; ++r) M[r + 4 * c] = -X[r + p * c];
-        M[(p + c) + 4 * c] = 1.0;
+    double z[PQ], x[PQ];
+#pragma unroll
+    for (int k = PQ - 1; k >= 0; --k) {
+        double acc = rhs[k];
+#pragma unroll
+        for (int c2 = k + 1; c2 < PQ; ++c2) acc -= K[k][c2] * z[c2];
+        z[k] = acc / K[k][k];
     }
-    for (int i = 0; i < m; ++i) G[i + 4 * i] = 1.0;
-    for (int c = 0; c < q; ++c) {
-        int len = m - c;
+#pragma unroll
+    for (int t = 0; t < PQ; ++t) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < PQ; ++k)
+            if (perm[k] == t) v = z[k];
+        x[t] = v;
+    }
+    // QR of [-X; I_Q] (M x Q) by Q Householder reflectors accumulated into G
+    double Mm[M][Q], G[M][M];
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) Mm[r][c] = -x[r + P * c];
+#pragma unroll
+        for (int r = 0; r < Q; ++r) Mm[P + r][c] = (r == c) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+#pragma unroll
+        for (int c = 0; c < M; ++c) G[r][c] = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
         double nrm2 = 0.0;
-        for (int r = 1; r < len; ++r) nrm2 += M[(c + r) + 4 * c] * M[(c + r) + 4 * c];
-        double x0 = M[c + 4 * c];
-        double v[4] = {1.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int r = c + 1; r < M; ++r) nrm2 += Mm[r][c] * Mm[r][c];
+        const double x0 = Mm[c][c];
+        double v[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) v[r] = 0.0;
+        v[c] = 1.0;
         double tau = 0.0;
         if (nrm2 > 0.0) {
-            double nrm = sqrt(x0 * x0 + nrm2);
-            double b = (x0 >= 0.0) ? -nrm : nrm;
-            tau = (b - x0) / b;
-            double sc = 1.0 / (x0 - b);
-            for (int r = 1; r < len; ++r) v[r] = M[(c + r) + 4 * c] * sc;
+            const double nrm = sqrt(x0 * x0 + nrm2);
+            const double bb = (x0 >= 0.0) ? -nrm : nrm;
+            tau = (bb - x0) / bb;
+            const double sc = 1.0 / (x0 - bb);
+#pragma unroll
+            for (int r = c + 1; r < M; ++r) v[r] = Mm[r][c] * sc;
         }
         if (tau != 0.0) {
-            for (int cc = c; cc < q; ++cc) {
-                double s = 0.0;
-                for (int r = 0; r < len; ++r) s += v[r] * M[(c + r) + 4 * cc];
-                s *= tau;
-                for (int r = 0; r < len; ++r) M[(c + r) + 4 * cc] -= s * v[r];
+#pragma unroll
+            for (int cc = c; cc < Q; ++cc) {
+                double acc = 0.0;
+#pragma unroll
+                for (int r = c; r < M; ++r) acc += v[r] * Mm[r][cc];
+                acc *= tau;
+#pragma unroll
+                for (int r = c; r < M; ++r) Mm[r][cc] -= acc * v[r];
             }
-            for (int rr = 0; rr < m; ++rr) {
-                double s = 0.0;
-                for (int r = 0; r < len; ++r) s += G[rr + 4 * (c + r)] * v[r];
-                s *= tau;
-                for (int r = 0; r < len; ++r) G[rr + 4 * (c + r)] -= s * v[r];
+#pragma unroll
+            for (int rr = 0; rr < M; ++rr) {
+                double acc = 0.0;
+#pragma unroll
+                for (int r = c; r < M; ++r) acc += G[rr][r] * v[r];
+                acc *= tau;
+#pragma unroll
+                for (int r = c; r < M; ++r) G[rr][r] -= acc * v[r];
             }
         }
     }
-    double DG[16];
-    for (int r = 0; r < m; ++r)
-        for (int c = 0; c < m; ++c) {
-            double s = 0.0;
-            for (int l = 0; l < m; ++l) s += D[r + 4 * l] * G[l + 4 * c];
-            DG[r + 4 * c] = s;
+    double DG[M][M], Dn[M][M];
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < M; ++l) acc += D[r][l] * G[l][c];
+            DG[r][c] = acc;
         }
-    for (int r = 0; r < m; ++r)
-        for (int c = 0; c < m; ++c) {
-            double s = 0.0;
-            for (int l = 0; l < m; ++l) s += G[l + 4 * r] * DG[l + 4 * c];
-            Dn[r + 4 * c] = s;
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < M; ++l) acc += G[l][r] * DG[l][c];
+            Dn[r][c] = acc;
         }
     double e1 = 0.0;
-    for (int c = 0; c < q; ++c)
-        for (int r = q; r < m; ++r) {
-            e1 = fmax(e1, fabs(Dn[r + 4 * c]));
-            Dn[r + 4 * c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < Q; ++c)
+#pragma unroll
+        for (int r = Q; r < M; ++r) {
+            e1 = fmax(e1, fabs(Dn[r][c]));
+            Dn[r][c] = 0.0;
         }
     double e2 = 0.0;
-    for (int r = 0; r < m; ++r)
-        for (int c = 0; c < m; ++c) {
-            double s = 0.0;
-            for (int l = 0; l < m; ++l) {
-                double t = 0.0;
-                for (int l2 = 0; l2 < m; ++l2) t += Dn[l + 4 * l2] * G[c + 4 * l2];
-                s += G[r + 4 * l] * t;
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                double tt = 0.0;
+#pragma unroll
+                for (int l2 = 0; l2 < M; ++l2) tt += Dn[l][l2] * G[c][l2];
+                acc += G[r][l] * tt;
             }
-            e2 = fmax(e2, fabs(s - D[r + 4 * c]));
+            e2 = fmax(e2, fabs(acc - D[r][c]));
         }
     if (e1 > thresh || e2 > thresh) return false;
-    // compact G to an m x m column-major array
-    double Gc[16];
-    for (int c = 0; c < m; ++c)
-        for (int r = 0; r < m; ++r) Gc[r + m * c] = G[r + 4 * c];
-    for (int i = 0; i < m * m; ++i) G[i] = Gc[i];
+    // standardize the new diagonal blocks; the rotations join G
+    if (Q == 2) {
+        double a = Dn[0][0], b = Dn[0][1], c = Dn[1][0], d = Dn[1][1], cs, sn;
+        std2_regs(a, b, c, d, cs, sn);
+#pragma unroll
+        for (int cc = 2; cc < M; ++cc) { // rows 0,1 right of the block
+            double y0 = Dn[0][cc], y1 = Dn[1][cc];
+            Dn[0][cc] = cs * y0 + sn * y1;
+            Dn[1][cc] = -sn * y0 + cs * y1;
+        }
+#pragma unroll
+        for (int rr = 0; rr < M; ++rr) {
+            double y0 = G[rr][0], y1 = G[rr][1];
+            G[rr][0] = cs * y0 + sn * y1;
+            G[rr][1] = -sn * y0 + cs * y1;
+        }
+        Dn[0][0] = a;
+        Dn[0][1] = b;
+        Dn[1][0] = c;
+        Dn[1][1] = d;
+    }
+    if (P == 2) {
+        const int q0 = Q;
+        double a = Dn[q0][q0], b = Dn[q0][q0 + 1], c = Dn[q0 + 1][q0], d = Dn[q0 + 1][q0 + 1], cs, sn;
+        std2_regs(a, b, c, d, cs, sn);
+#pragma unroll
+        for (int rr = 0; rr < Q; ++rr) { // rows above the block, its two columns
+            double y0 = Dn[rr][q0], y1 = Dn[rr][q0 + 1];
+            Dn[rr][q0] = cs * y0 + sn * y1;
+            Dn[rr][q0 + 1] = -sn * y0 + cs * y1;
+        }
+#pragma unroll
+        for (int rr = 0; rr < M; ++rr) {
+            double y0 = G[rr][q0], y1 = G[rr][q0 + 1];
+            G[rr][q0] = cs * y0 + sn * y1;
+            G[rr][q0 + 1] = -sn * y0 + cs * y1;
+        }
+        Dn[q0][q0] = a;
+        Dn[q0][q0 + 1] = b;
+        Dn[q0 + 1][q0] = c;
+        Dn[q0 + 1][q0 + 1] = d;
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            Gout[r + M * c] = G[r][c];
+            Dout[r + 4 * c] = Dn[r][c];
+        }
     return true;
 }
 
@@ -718,8 +1037,51 @@ __device__ int swap_blocks(SmemCore &S, double *T, int ldt, int nt, double *Z, i
                            int q, double smlnum)
 {
     int m = p + q;
+    if (p == 1 && q == 1) {
+        // two 1x1 blocks: every thread forms the rotation from the same entries
+        const double t11 = T[j + j * ldt], t12 = T[j + (j + 1) * ldt], t22 = T[(j + 1) + (j + 1) * ldt];
+        const double rr = hypot(t12, t22 - t11);
+        double cs = 1.0, sn = 0.0;
+        if (rr != 0.0) {
+            cs = t12 / rr;
+            sn = (t22 - t11) / rr;
+        }
+        const double n01 = cs * (-t11 * sn + t12 * cs) + sn * (t22 * cs);
+        __syncthreads(); // every thread has read the block before it is overwritten
+        const int ncl = max(nt - (j + 2), 0);
+        const int total = ncl + j + nz;
+        for (int it = threadIdx.x; it < total; it += NT) {
+            if (it < ncl) {
+                const int c = j + 2 + it;
+                double x = T[j + c * ldt], y = T[(j + 1) + c * ldt];
+                T[j + c * ldt] = cs * x + sn * y;
+                T[(j + 1) + c * ldt] = -sn * x + cs * y;
+            } else {
+                const int rr2 = it - ncl;
+                double *M = (rr2 < j) ? T + rr2 : Z + (rr2 - j);
+                const int ld = (rr2 < j) ? ldt : ldz;
+                double x = M[j * ld], y = M[(j + 1) * ld];
+                M[j * ld] = cs * x + sn * y;
+                M[(j + 1) * ld] = -sn * x + cs * y;
+            }
+        }
+        if (threadIdx.x == 0) {
+            T[j + j * ldt] = t22;
+            T[j + (j + 1) * ldt] = n01;
+            T[(j + 1) + j * ldt] = 0.0;
+            T[(j + 1) + (j + 1) * ldt] = t11;
+        }
+        __syncthreads();
+        return 0;
+    }
     if (threadIdx.x == 0) {
-        bool ok = swap_transform(T, ldt, j, p, q, smlnum, S.G, S.Dn);
+        bool ok;
+        if (p == 1)
+            ok = swap_xform<1, 2>(T, ldt, j, smlnum, S.G, S.Dn);
+        else if (q == 1)
+            ok = swap_xform<2, 1>(T, ldt, j, smlnum, S.G, S.Dn);
+        else
+            ok = swap_xform<2, 2>(T, ldt, j, smlnum, S.G, S.Dn);
         S.ic[2] = ok ? 1 : 0;
     }
     __syncthreads();
@@ -735,41 +1097,50 @@ __device__ int swap_blocks(SmemCore &S, double *T, int ldt, int nt, double *Z, i
         double x[4], y[4];
         if (it < ncl) {
             int c = j + m + it;
-            for (int r = 0; r < m; ++r) x[r] = T[(j + r) + c * ldt];
-            for (int r = 0; r < m; ++r) {
-                double s = 0.0;
-                for (int i = 0; i < m; ++i) s += S.G[i + m * r] * x[i];
-                y[r] = s;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) x[r] = (r < m) ? T[(j + r) + c * ldt] : 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (i < m && r < m) acc += S.G[i + m * r] * x[i];
+                y[r] = acc;
             }
-            for (int r = 0; r < m; ++r) T[(j + r) + c * ldt] = y[r];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r < m) T[(j + r) + c * ldt] = y[r];
         } else {
-            double *M;
+            double *Mx;
             int ld;
             int rr = it - max(ncl, 0);
             if (rr < j) {
-                M = T + rr;
+                Mx = T + rr;
                 ld = ldt;
             } else {
-                M = Z + (rr - j);
+                Mx = Z + (rr - j);
                 ld = ldz;
             }
-            for (int c = 0; c < m; ++c) x[c] = M[(j + c) * ld];
-            for (int c = 0; c < m; ++c) {
-                double s = 0.0;
-                for (int l = 0; l < m; ++l) s += x[l] * S.G[l + m * c];
-                y[c] = s;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) x[c] = (c < m) ? Mx[(j + c) * ld] : 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double acc = 0.0;
+#pragma unroll
+                for (int l = 0; l < 4; ++l)
+                    if (l < m && c < m) acc += x[l] * S.G[l + m * c];
+                y[c] = acc;
             }
-            for (int c = 0; c < m; ++c) M[(j + c) * ld] = y[c];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (c < m) Mx[(j + c) * ld] = y[c];
         }
     }
-    __syncthreads();
     if (threadIdx.x < m * m) {
         int r = threadIdx.x % m, c = threadIdx.x / m;
         T[(j + r) + (j + c) * ldt] = S.Dn[r + 4 * c];
     }
     __syncthreads();
-    if (q == 2) std_block(S, T, ldt, nt, Z, ldz, nz, j);
-    if (p == 2) std_block(S, T, ldt, nt, Z, ldz, nz, j + q);
     return 0;
 }
 
@@ -890,6 +1261,7 @@ __device__ double restore_lds(Smem &S, double *T, int ldt, int nt, int ns, doubl
             c0 = 0;
         }
         __syncthreads();
+        if (threadIdx.x == 0) S.flops += 4.0 * len * (double)((nt - c0) + ns + nz);
         if (tau != 0.0) {
             // left: rows r0..r0+len-1, columns c0..nt-1
             for (int c = c0 + (int)threadIdx.x; c < nt; c += NT) {
@@ -991,8 +1363,12 @@ __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int i
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem &S = *reinterpret_cast<Smem *>(smem_raw);
     const int tid = threadIdx.x;
+    const long long t_start = wall_clock64();
     // locate the active block
-    if (tid == 0) S.ic[3] = ilo;
+    if (tid == 0) {
+        S.ic[3] = ilo;
+        S.flops = 0.0;
+    }
     __syncthreads();
     for (int l = kbot - tid; l > ilo; l -= NT) {
         double h = H[l + (int64_t)(l - 1) * ld];
@@ -1040,11 +1416,14 @@ __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int i
     identity_lds(S.Z, LDM, m, m);
     __syncthreads();
     int info = qr_small(S, S.A, LDM, m, S.Z, LDM, m, smlnum, itmax, nsmall);
+    const long long t_schur = wall_clock64();
+    long long t_defl = t_schur, t_rest = t_schur;
     int ns = 0, nd = m;
     double beta = 0.0;
     if (!small) {
         // spike = s * Z(0,:); bottom-up test; failures move to the top
         ns = aed_deflate(S, S.A, LDM, m, S.Z, LDM, m, 0, s, info > 0 ? info : 0, smlnum);
+        t_defl = wall_clock64();
         nd = m - ns;
         if (tid == 0) {
             // candidates: eigenvalues of the undeflated blocks, diagonal order
@@ -1075,6 +1454,7 @@ __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int i
             if (ns >= 1) beta = s * S.Z[0];
             if (ns > 1 && s != 0.0) beta = restore_lds(S, S.A, LDM, m, ns, S.Z, LDM, m, 0, s);
         }
+        t_rest = wall_clock64();
     }
     __syncthreads();
     const bool changed = small || nd > 0;
@@ -1096,6 +1476,11 @@ __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int i
         st->ncand = small ? 0 : ns;
         st->info = small ? (info > 0 ? kw + info : 0) : 0;
         st->changed = changed ? 1 : 0;
+        st->beta = S.flops;
+        st->tick[0] = t_schur - t_start;
+        st->tick[1] = t_defl - t_schur;
+        st->tick[2] = t_rest - t_defl;
+        st->tick[3] = wall_clock64() - t_start;
     }
 }
 

@@ -30,25 +30,45 @@ def read() -> dict:
             for i, c in enumerate(CLASSES)}
 
 
+def lds_split() -> dict:
+    """Fractions of the LDS iteration kernel's device time spent in the Schur
+    solve, the reordering and the Hessenberg restoration."""
+    t = (ctypes.c_int64 * 4)()
+    lib().hqr_profile_ticks(t, 4)
+    tot = max(int(t[3]), 1)
+    return {"schur": t[0] / tot, "reorder": t[1] / tot, "restore": t[2] / tot}
+
+
 def summary(prof: dict, steps: int) -> dict:
     return {c: {"ms_per_step": v["ms"] / max(steps, 1), "launches_per_step": v["launches"] / max(steps, 1),
                 "kernel": KERNELS[c]} for c, v in prof.items()}
 
 
-def roofline(prof: dict, steps: int) -> dict:
-    """Roofline entry for the update products (the FP64-MFMA kernel): counted
-    algorithmic flops per launch / average launch duration, against the FP64
-    matrix peak; the dominant class by time is reported alongside."""
-    dom = max(prof, key=lambda c: prof[c]["ms"])
-    g = prof["update_gemm"]
+def _entry(prof: dict, cls: str, steps: int) -> dict:
+    g = prof[cls]
+    bound = "mfma" if cls == "update_gemm" else "alu"
+    out = {"bound": bound, "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
+           "traffic": None, "kernel": KERNELS[cls], "class": cls}
     if g["launches"] == 0 or g["ms"] <= 0:
-        return {"bound": "mfma", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
-                "traffic": None, "kernel": "k_update", "dominant_class": dom}
+        return out
     avg_s = g["ms"] / g["launches"] / 1e3
-    flops_per_launch = g["flops"] / g["launches"]
-    ach = flops_per_launch / avg_s / 1e12
-    return {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": ach / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "k_update",
-            "avg_launch_us": avg_s * 1e6, "flops_per_launch": flops_per_launch,
-            "bytes_per_launch": g["bytes"] / g["launches"],
-            "dominant_class": dom, "dominant_ms_per_step": prof[dom]["ms"] / max(steps, 1)}
+    fpl = g["flops"] / g["launches"]
+    ach = fpl / avg_s / 1e12
+    out.update({"achieved": ach, "frac": ach / FP64_PEAK_TFLOPS, "avg_launch_us": avg_s * 1e6,
+                "flops_per_launch": fpl, "bytes_per_launch": g["bytes"] / g["launches"],
+                "launches_per_step": g["launches"] / max(steps, 1), "ms_per_step": g["ms"] / max(steps, 1)})
+    if bound == "alu":
+        # one workgroup runs on one of the 256 CUs: its own ceiling is 1/256 of the chip
+        out["peak_one_cu"] = FP64_PEAK_TFLOPS / 256.0
+        out["frac_one_cu"] = ach / (FP64_PEAK_TFLOPS / 256.0)
+    return out
+
+
+def roofline(prof: dict, steps: int) -> dict:
+    """Roofline entry of the dominant kernel class by time (counted algorithmic
+    flops per launch / average launch duration vs the FP64 peak), with the
+    FP64-MFMA update kernel reported alongside."""
+    dom = max(prof, key=lambda c: prof[c]["ms"])
+    out = _entry(prof, dom, steps)
+    out["mfma_update"] = _entry(prof, "update_gemm", steps)
+    return out

@@ -57,15 +57,20 @@ def hess_lu_residual(H, lam, iters=1, seed=0):
     U_ = np.triu(LU)
     rng = np.random.default_rng(seed)
     x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    import scipy.linalg as sla
     for _ in range(iters):
-        b = x.copy()
+        b = x / np.linalg.norm(x) * 1e-200  # scaled so that huge solutions stay finite
         for k in range(n - 1):  # apply the row operations to b
             if piv[k]:
                 b[k], b[k + 1] = b[k + 1], b[k]
             b[k + 1] -= mult[k] * b[k]
-        import scipy.linalg as sla
-        x = sla.solve_triangular(U_, b)
-        x /= np.linalg.norm(x)
+        with np.errstate(over="ignore", invalid="ignore"):
+            x = sla.solve_triangular(U_, b, check_finite=False)
+        nx = np.linalg.norm(x)
+        if not np.isfinite(nx):
+            # ||x|| > 1e108 for ||b|| = 1e-200: sigma_min(H - lam I) < 1e-308
+            return 0.0
+        x /= nx
     r = A @ x
     return np.linalg.norm(r)
 
