@@ -116,9 +116,14 @@ int hqr_last_stats(int64_t *stats, int len);
 int hqr_profile_enable(int on);
 int hqr_profile_reset(void);
 int hqr_profile_read(double *ms, int64_t *launches, double *flops, double *bytes, int nclass);
-/* Device wall-clock ticks spent inside the one-workgroup LDS iteration kernel,
- * split into Schur solve, reordering (spike test and swaps), Hessenberg
- * restoration and total, summed over the profiled launches. */
+/* Counters of the one-workgroup LDS iteration kernel summed over the profiled
+ * launches: [0..3] device wall-clock ticks (100 MHz) of the Schur solve, the
+ * reordering (spike test and swaps), the Hessenberg restoration and the whole
+ * kernel; [4] barrier-separated bulge-chase phases; [5] single-bulge steps;
+ * [6] adjacent-block swaps; [7] launches that solved a small block; [8]
+ * launches that performed an AED step; [9] phases of the pipelined
+ * reordering.  Writes min(len, 10) entries and returns that count, or -1 on
+ * NULL / len <= 0. */
 int hqr_profile_ticks(int64_t *ticks, int len);
 
 /* Free per-device workspace and helper streams. */

@@ -28,7 +28,11 @@ struct IterStatus {
     int ncand;   // number of candidate eigenvalues in cr/ci
     int info;    // 0, or >0 when the small solver did not converge
     int changed; // 1 when H was modified and the factor must be propagated
-    int pad;
+    int pad;     // scratch word for small device-to-host reads
+    int nphase;  // LDS iteration kernel: barrier-separated bulge-chase phases
+    int nbstep;  // LDS iteration kernel: single-bulge steps (a phase moves one or more bulges)
+    int nswap;   // LDS iteration kernel: adjacent-block swaps attempted
+    int nrphase; // LDS iteration kernel: phases of the pipelined reordering
     double beta; // new subdiagonal entry left of a large AED window after restoration;
                  // for the LDS iteration kernel: its algorithmic flop count
     long long tick[4]; // LDS iteration kernel: wall-clock ticks of Schur solve, reordering, restoration, total

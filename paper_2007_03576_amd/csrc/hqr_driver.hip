@@ -98,6 +98,7 @@ Workspace g_ws[16];
 
 // ---- optional kernel-class timing with HIP events (measurement tools) ----
 constexpr int NCLASS = 5; // 0 LDS iteration, 1 chase windows, 2 update products, 3 large-AED kernels, 4 other
+constexpr int NTICK = 10;
 struct ProfRec {
     int cls;
     hipEvent_t a, b;
@@ -109,7 +110,10 @@ std::vector<ProfRec> g_prof;
 std::vector<hipEvent_t> g_prof_pool;
 double g_prof_ms[NCLASS], g_prof_flops[NCLASS], g_prof_bytes[NCLASS];
 int64_t g_prof_n[NCLASS];
-long long g_prof_ticks[4]; // LDS iteration: Schur, reordering, restoration, total (device wall clock)
+// LDS iteration kernel: wall-clock ticks of Schur solve, reordering, restoration and total, then
+// bulge-chase phases, single-bulge steps, swaps, launches of the small-solve and AED kinds, and
+// phases of the pipelined reordering
+long long g_prof_ticks[NTICK];
 
 hipEvent_t prof_event()
 {
@@ -153,11 +157,16 @@ void prof_set_flops(int id, double flops)
     g_prof[id].flops = flops;
 }
 
-void prof_add_ticks(const long long *t)
+void prof_add_ticks(const IterStatus &S)
 {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    for (int i = 0; i < 4; ++i) g_prof_ticks[i] += t[i];
+    for (int i = 0; i < 4; ++i) g_prof_ticks[i] += S.tick[i];
+    g_prof_ticks[4] += S.nphase;
+    g_prof_ticks[5] += S.nbstep;
+    g_prof_ticks[6] += S.nswap;
+    g_prof_ticks[S.kind == 0 ? 7 : 8] += 1;
+    g_prof_ticks[9] += S.nrphase;
 }
 
 // fold finished records into the per-class totals
@@ -642,7 +651,7 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
             if (C.stats) C.stats[6]++;
             if (read_status(C, nwp)) return -1;
             prof_set_flops(pid, S.beta);
-            prof_add_ticks(S.tick);
+            prof_add_ticks(S);
             ktop = S.ktop;
             if (S.kind == 0) {
                 if (S.info > 0) {
@@ -681,7 +690,7 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
                 prof_end(pid, C.hi, 0.0, 0.0);
                 if (read_status(C, MMAX)) return -1;
                 prof_set_flops(pid, S.beta);
-                prof_add_ticks(S.tick);
+                prof_add_ticks(S);
                 if (S.kind == 0) {
                     if (S.info > 0) {
                         *info_out = S.info;
@@ -937,14 +946,14 @@ int hqr_profile_reset(void)
         g_prof_ms[c] = g_prof_flops[c] = g_prof_bytes[c] = 0.0;
         g_prof_n[c] = 0;
     }
-    for (int i = 0; i < 4; ++i) g_prof_ticks[i] = 0;
+    for (int i = 0; i < NTICK; ++i) g_prof_ticks[i] = 0;
     return 0;
 }
 
 int hqr_profile_ticks(int64_t *ticks, int len)
 {
     if (!ticks || len <= 0) return -1;
-    int m = std::min(len, 4);
+    int m = std::min(len, NTICK);
     for (int i = 0; i < m; ++i) ticks[i] = g_prof_ticks[i];
     return m;
 }

@@ -27,17 +27,27 @@ namespace hqr {
 constexpr double kU = 2.220446049250313080847e-16; // unit roundoff 2^-52
 
 // Small per-workgroup state used by every solver piece.
+// State of the pipelined deflation check and reordering of an AED window.
+constexpr int MV = 32; // most block moves in flight
+struct ReorderState {
+    double G[MV * 16];               // exchange of each lane of the current phase (order m, column major)
+    int pos[2][MV], sz[MV], dst[MV]; // moves in flight (ring indexed by move id), position double buffered
+    int sj[MV], sm[MV];              // exchange of each lane: first row and order (0: none)
+    int roff[MV + 1], coff[MV + 1];  // prefix sums of the row and column work items per lane
+    int head, tail, ns, ilst, halt, chk_done, done, rtot, ctot;
+};
+
 struct SmemCore {
     double bv1[GMAX], bv2[GMAX], btau[GMAX];
     int bk[GMAX], bm[GMAX], bc0[GMAX];
     double sr[2 * GMAX], si[2 * GMAX];
     double red[NT / 64];
-    double G[16];
-    double Dn[16];
     double sc[8];
     int ic[8];
     double shb[16 * 16]; // trailing block whose eigenvalues become the shifts of a multishift sweep
     double flops;        // algorithmic flops of the reflector applications (thread 0 counts)
+    int nphase, nbstep, nswap, nrphase; // event counters (thread 0 counts)
+    ReorderState ro;
 };
 
 // LDS-resident matrix and accumulated factor for orders <= MMAX.
@@ -240,7 +250,7 @@ __device__ inline void refl3(int m, double tau, double v1, double v2, double &y0
 // single bulge every thread computes the reflector itself (no barrier before
 // the products) and the bulge column is written one step later, when no
 // thread reads it any more.
-__device__ void chain_chase(SmemCore &S, double *A, int lda, int off, int ktop, int kbot, int p0, int nsteps,
+__device__ __forceinline__ void chain_chase(SmemCore &S, double *A, int lda, int off, int ktop, int kbot, int p0, int nsteps,
                             int kend, int nb, int colhi, double *Z, int ldz, int nz)
 {
     const int tid = threadIdx.x;
@@ -293,6 +303,10 @@ __device__ void chain_chase(SmemCore &S, double *A, int lda, int off, int ktop, 
         if (bhi < 0) {
             if (nb > 1) __syncthreads();
             continue;
+        }
+        if (tid == 0) {
+            S.nphase += 1;
+            S.nbstep += bhi - blo + 1;
         }
         // geometry of this step (uniform across threads)
         auto KL = [&](int b) { return nb == 1 ? r_kl : S.bk[b]; };
@@ -456,7 +470,7 @@ __device__ void chain_chase(SmemCore &S, double *A, int lda, int off, int ktop, 
 
 // Largest l in (lo,hi] whose subdiagonal A[l,l-1] is zero or negligible
 // (then set to zero); lo if there is none.
-__device__ int find_split(SmemCore &S, double *A, int lda, int lo, int hi, double smlnum)
+__device__ __forceinline__ int find_split(SmemCore &S, double *A, int lda, int lo, int hi, double smlnum)
 {
     if (threadIdx.x == 0) S.ic[0] = lo;
     __syncthreads();
@@ -476,7 +490,7 @@ __device__ int find_split(SmemCore &S, double *A, int lda, int lo, int hi, doubl
 
 // Standardize the 2x2 block at (k,k+1): rows k,k+1 over columns k..ncol-1,
 // columns over rows 0..k+1, Z columns over nz rows.  Returns 1 for a complex pair.
-__device__ int std_block(SmemCore &S, double *A, int lda, int ncol, double *Z, int ldz, int nz, int k)
+__device__ __forceinline__ int std_block(SmemCore &S, double *A, int lda, int ncol, double *Z, int ldz, int nz, int k)
 {
     for (int pass = 0; pass < 3; ++pass) {
         if (threadIdx.x == 0) {
@@ -534,7 +548,7 @@ __device__ int std_block(SmemCore &S, double *A, int lda, int ncol, double *Z, i
 
 // One Francis double-shift iteration on the active block [l,i] (full T and Z):
 // shifts from the trailing 2x2 (exceptional shifts at iterations 10 and 20).
-__device__ void ds_step(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, int l, int i, int its)
+__device__ __forceinline__ void ds_step(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, int l, int i, int its)
 {
     if (threadIdx.x == 0) {
         double a, b, c, d;
@@ -574,7 +588,7 @@ __device__ void ds_step(SmemCore &S, double *A, int lda, int m, double *Z, int l
 
 // Francis double-shift QR on the whole matrix A (order m, full T), Z accumulates.
 // Returns 0 or 1 + the bottom row of the block that did not converge.
-__device__ int qr_ds(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, double smlnum,
+__device__ __forceinline__ int qr_ds(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, double smlnum,
                      int64_t itmax_in)
 {
     int64_t itmax = 30 * (int64_t)max(10, m);
@@ -606,7 +620,7 @@ __device__ int qr_ds(SmemCore &S, double *A, int lda, int m, double *Z, int ldz,
 // become the shifts of a chain of ns/2 tightly coupled bulges chased through
 // the block in one pass (Sec. 2.3); otherwise, and at the exceptional-shift
 // iterations, a double-shift step.  nsmax <= 2 gives the plain Francis QR.
-__device__ int qr_small(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, double smlnum,
+__device__ __forceinline__ int qr_small(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, double smlnum,
                         int64_t itmax_in, int nsmax = 2)
 {
     if (nsmax <= 2) return qr_ds(S, A, lda, m, Z, ldz, nz, smlnum, itmax_in);
@@ -692,59 +706,6 @@ __device__ int qr_small(SmemCore &S, double *A, int lda, int m, double *Z, int l
     return 0;
 }
 
-// Solve K y = r (order q <= 4, K row stride 4) by Gaussian elimination with
-// complete pivoting; pivots below smin are replaced by smin.
-__device__ void solve_small(int q, double *K, double *r, double *y, double smin)
-{
-    int pc[4] = {0, 1, 2, 3};
-    for (int k = 0; k < q; ++k) {
-        int br = k, bc = k;
-        double best = -1.0;
-        for (int i = k; i < q; ++i)
-            for (int j = k; j < q; ++j) {
-                double v = fabs(K[i * 4 + j]);
-                if (v > best) {
-                    best = v;
-                    br = i;
-                    bc = j;
-                }
-            }
-        if (br != k) {
-            for (int j = 0; j < q; ++j) {
-                double t = K[k * 4 + j];
-                K[k * 4 + j] = K[br * 4 + j];
-                K[br * 4 + j] = t;
-            }
-            double t = r[k];
-            r[k] = r[br];
-            r[br] = t;
-        }
-        if (bc != k) {
-            for (int i = 0; i < q; ++i) {
-                double t = K[i * 4 + k];
-                K[i * 4 + k] = K[i * 4 + bc];
-                K[i * 4 + bc] = t;
-            }
-            int t = pc[k];
-            pc[k] = pc[bc];
-            pc[bc] = t;
-        }
-        if (fabs(K[k * 4 + k]) < smin) K[k * 4 + k] = (K[k * 4 + k] >= 0.0) ? smin : -smin;
-        for (int i = k + 1; i < q; ++i) {
-            double f = K[i * 4 + k] / K[k * 4 + k];
-            for (int j = k; j < q; ++j) K[i * 4 + j] -= f * K[k * 4 + j];
-            r[i] -= f * r[k];
-        }
-    }
-    double z[4];
-    for (int k = q - 1; k >= 0; --k) {
-        double s = r[k];
-        for (int j = k + 1; j < q; ++j) s -= K[k * 4 + j] * z[j];
-        z[k] = s / K[k * 4 + k];
-    }
-    for (int k = 0; k < q; ++k) y[pc[k]] = z[k];
-}
-
 // Standardizing rotation of a 2x2 block held in registers: returns the total
 // rotation (cs, sn) and leaves the standardized values in (a, b, c, d).
 __device__ inline void std2_regs(double &a, double &b, double &c, double &d, double &cst, double &snt)
@@ -776,14 +737,16 @@ __device__ inline void std2_regs(double &a, double &b, double &c, double &d, dou
 
 // One thread: orthogonal G exchanging the blocks of D = T(j:j+M, j:j+M)
 // (top block P x P, bottom block Q x Q; at least one of them 2x2), with the
-// two new diagonal blocks standardized.  Dn = G^T D G with the (2,1) block
-// exactly zero.  Bai-Demmel: solve A11 X - X A22 = A12, QR of [-X; I_Q],
+// two new diagonal blocks standardized.  On success Dn = G^T D G, with its
+// (2,1) block exactly zero, replaces D in T and G goes to Gout (column
+// major, order M); on rejection nothing is written.  Bai-Demmel: solve A11 X - X A22 = A12, QR of [-X; I_Q],
 // weak (new (2,1) block) and strong (reconstruction) stability tests.
 // Sizes are compile-time so every array stays in registers; pivot choices
 // are applied through unrolled selects.
 template <int P, int Q>
-__device__ bool swap_xform(const double *T, int ldt, int j, double smlnum, double *Gout, double *Dout)
+__device__ bool swap_xform(double *Tw, int ldt, int j, double smlnum, double *Gout)
 {
+    const double *T = Tw;
     constexpr int M = P + Q, PQ = P * Q;
     double D[M][M];
     double dnorm = 0.0;
@@ -1026,181 +989,288 @@ __device__ bool swap_xform(const double *T, int ldt, int j, double smlnum, doubl
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             Gout[r + M * c] = G[r][c];
-            Dout[r + 4 * c] = Dn[r][c];
+            Tw[(j + r) + (j + c) * ldt] = Dn[r][c];
         }
     return true;
 }
 
-// Exchange the blocks of sizes p and q at row j of the LDS matrix T (order nt);
-// Z (nz rows) accumulates.  Returns 0 on success, 1 if rejected.
-__device__ int swap_blocks(SmemCore &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int j, int p,
-                           int q, double smlnum)
+// Bottom-up deflation test of the candidates of the quasi-triangular T (order
+// nt) with spike entries sp_k = spscale * Z[sprow + k*ldz]; each failed
+// candidate moves up to the first free position of the undeflated region,
+// the remaining candidates shift down (Sec. 2.4, and the concurrent deflate
+// and reordering windows of the parallel AED, Sec. 3.3).
+//
+// The moves are pipelined: a failed candidate starts to move as soon as it is
+// examined, and the next candidate (the block now below it) is examined as
+// soon as its own entries are final, i.e. after the first exchange of the move
+// above it.  Every phase performs, for all moves at once, one exchange of
+// adjacent blocks per move whose block above is free, so a move trails the one
+// ahead of it by one block.  Exchanges of one phase touch disjoint diagonal
+// ranges: their left products (rows) are applied first, then their right
+// products (columns of T above the range and of Z), so every entry sees the
+// same products as in the one-move-at-a-time order; only the rounding order
+// of the entries shared by two exchanges differs.  Wave 0 schedules: lane i
+// owns the i-th active move, the lane after the last one examines candidates;
+// each lane also forms its exchange (rotation, or Bai-Demmel with standardized
+// blocks).  A rejected exchange, or a moving 2x2 block that splits, halts the
+// reordering after its phase; T stays quasi-triangular and everything above
+// the deflated bottom counts as undeflated.  Returns the number of undeflated
+// leading rows.
+__device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int sprow,
+                           double spscale, int ilst0, double smlnum)
 {
-    int m = p + q;
-    if (p == 1 && q == 1) {
-        // two 1x1 blocks: every thread forms the rotation from the same entries
-        const double t11 = T[j + j * ldt], t12 = T[j + (j + 1) * ldt], t22 = T[(j + 1) + (j + 1) * ldt];
-        const double rr = hypot(t12, t22 - t11);
-        double cs = 1.0, sn = 0.0;
-        if (rr != 0.0) {
-            cs = t12 / rr;
-            sn = (t22 - t11) / rr;
-        }
-        const double n01 = cs * (-t11 * sn + t12 * cs) + sn * (t22 * cs);
-        __syncthreads(); // every thread has read the block before it is overwritten
-        const int ncl = max(nt - (j + 2), 0);
-        const int total = ncl + j + nz;
-        for (int it = threadIdx.x; it < total; it += NT) {
-            if (it < ncl) {
-                const int c = j + 2 + it;
-                double x = T[j + c * ldt], y = T[(j + 1) + c * ldt];
-                T[j + c * ldt] = cs * x + sn * y;
-                T[(j + 1) + c * ldt] = -sn * x + cs * y;
-            } else {
-                const int rr2 = it - ncl;
-                double *M = (rr2 < j) ? T + rr2 : Z + (rr2 - j);
-                const int ld = (rr2 < j) ? ldt : ldz;
-                double x = M[j * ld], y = M[(j + 1) * ld];
-                M[j * ld] = cs * x + sn * y;
-                M[(j + 1) * ld] = -sn * x + cs * y;
-            }
-        }
-        if (threadIdx.x == 0) {
-            T[j + j * ldt] = t22;
-            T[j + (j + 1) * ldt] = n01;
-            T[(j + 1) + j * ldt] = 0.0;
-            T[(j + 1) + (j + 1) * ldt] = t11;
-        }
-        __syncthreads();
-        return 0;
-    }
-    if (threadIdx.x == 0) {
-        bool ok;
-        if (p == 1)
-            ok = swap_xform<1, 2>(T, ldt, j, smlnum, S.G, S.Dn);
-        else if (q == 1)
-            ok = swap_xform<2, 1>(T, ldt, j, smlnum, S.G, S.Dn);
-        else
-            ok = swap_xform<2, 2>(T, ldt, j, smlnum, S.G, S.Dn);
-        S.ic[2] = ok ? 1 : 0;
+    ReorderState &R = S.ro;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        R.head = R.tail = 0;
+        R.ns = nt;
+        R.ilst = ilst0;
+        R.halt = 0;
+        R.chk_done = (ilst0 >= nt) ? 1 : 0;
+        R.done = 0;
     }
     __syncthreads();
-    if (!S.ic[2]) {
+    int par = 0, nphase = 0;
+    while (!R.done) {
+        if (tid < 64) {
+            const int lane = tid;
+            // (a) scheduling from the state left by the previous phase; no LDS
+            // writes until every lane has read what it needs
+            const int head = R.head, tail = R.tail, nact = tail - head;
+            const bool halt0 = R.halt != 0;
+            bool chk_done = R.chk_done != 0;
+            int ns = R.ns, ilst = R.ilst;
+            int slot = -1, pos = 0, sz = 0, dst = 0;
+            int sj = -1, sp = 0;
+            bool fin = false, bad = false, created = false;
+            if (!halt0 && lane < nact) {
+                const int id = head + lane;
+                slot = id % MV;
+                pos = R.pos[par][slot];
+                sz = R.sz[slot];
+                dst = R.dst[slot];
+                if (pos == dst) {
+                    fin = true;
+                } else {
+                    const int lim = (lane == 0) ? 0 : R.pos[par][(id - 1) % MV] + R.sz[(id - 1) % MV];
+                    const int above = (pos >= 2 && T[(pos - 1) + (pos - 2) * ldt] != 0.0) ? 2 : 1;
+                    const int j = pos - above;
+                    if (j < dst) {
+                        bad = true;
+                    } else if (j >= lim) {
+                        sj = j;
+                        sp = above;
+                    }
+                }
+            }
+            if (!halt0 && !chk_done && lane == nact && nact < MV) {
+                const int lim2 = (nact > 0) ? R.pos[par][(tail - 1) % MV] + R.sz[(tail - 1) % MV] : 0;
+                for (;;) {
+                    if (ilst >= ns) {
+                        chk_done = true;
+                        break;
+                    }
+                    const bool two = (ns >= 2 && T[(ns - 1) + (ns - 2) * ldt] != 0.0);
+                    if (two && ns - 2 < ilst) {
+                        chk_done = true;
+                        break;
+                    }
+                    const int csz = two ? 2 : 1, k = ns - 1, cand = ns - csz;
+                    if (cand < lim2) break; // still touched by the move above it
+                    bool defl;
+                    if (!two) {
+                        const double foo = fabs(T[k + k * ldt]);
+                        defl = fabs(spscale * Z[sprow + k * ldz]) <= fmax(smlnum, kU * foo);
+                    } else {
+                        const double hh = sqrt(fabs(T[k + k * ldt] * T[(k - 1) + (k - 1) * ldt])) +
+                                          sqrt(fabs(T[(k - 1) + k * ldt] * T[k + (k - 1) * ldt]));
+                        const double spk = fmax(fabs(spscale * Z[sprow + k * ldz]),
+                                                fabs(spscale * Z[sprow + (k - 1) * ldz]));
+                        defl = spk <= fmax(smlnum, kU * hh);
+                    }
+                    if (defl) {
+                        ns -= csz;
+                        continue;
+                    }
+                    if (cand == ilst) { // already in place
+                        ilst += csz;
+                        continue;
+                    }
+                    created = true;
+                    slot = tail % MV;
+                    pos = cand;
+                    sz = csz;
+                    dst = ilst;
+                    const int above = (cand >= 2 && T[(cand - 1) + (cand - 2) * ldt] != 0.0) ? 2 : 1;
+                    const int j = cand - above;
+                    if (j < ilst) bad = true;
+                    else if (j >= lim2) {
+                        sj = j;
+                        sp = above;
+                    }
+                    ilst += csz;
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // (b) the exchanges: each swapping lane forms its transformation,
+            // writes the new diagonal block into T and G into its slot
+            bool ok = true, split = false;
+            if (sj >= 0) {
+                double *G = R.G + lane * 16;
+                if (sp == 1 && sz == 1) {
+                    const double t11 = T[sj + sj * ldt], t12 = T[sj + (sj + 1) * ldt];
+                    const double t22 = T[(sj + 1) + (sj + 1) * ldt];
+                    const double rr = hypot(t12, t22 - t11);
+                    double cs = 1.0, sn = 0.0;
+                    if (rr != 0.0) {
+                        cs = t12 / rr;
+                        sn = (t22 - t11) / rr;
+                    }
+                    G[0] = cs;
+                    G[1] = sn;
+                    G[2] = -sn;
+                    G[3] = cs;
+                    T[sj + sj * ldt] = t22;
+                    T[sj + (sj + 1) * ldt] = cs * (-t11 * sn + t12 * cs) + sn * (t22 * cs);
+                    T[(sj + 1) + sj * ldt] = 0.0;
+                    T[(sj + 1) + (sj + 1) * ldt] = t11;
+                } else if (sp == 1) {
+                    ok = swap_xform<1, 2>(T, ldt, sj, smlnum, G);
+                } else if (sz == 1) {
+                    ok = swap_xform<2, 1>(T, ldt, sj, smlnum, G);
+                } else {
+                    ok = swap_xform<2, 2>(T, ldt, sj, smlnum, G);
+                }
+                if (ok && sz == 2 && T[(sj + 1) + sj * ldt] == 0.0) split = true;
+            }
+            const bool moved = (sj >= 0) && ok;
+            if (slot >= 0) {
+                R.pos[par ^ 1][slot] = moved ? sj : pos;
+                if (created) {
+                    R.sz[slot] = sz;
+                    R.dst[slot] = dst;
+                }
+            }
+            // finished moves leave the head of the queue in order
+            const unsigned long long finm = __ballot(fin || (moved && sj == dst));
+            const unsigned long long stop = __ballot(bad || !ok || split);
+            const unsigned long long tried = __ballot(sj >= 0);
+            // prefix sums of the row and column work items of this phase
+            const int m = sp + sz;
+            int rc = moved ? (nt - (sj + m)) : 0, cc = moved ? (sj + nz) : 0;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int r2 = __shfl_up(rc, d), c2 = __shfl_up(cc, d);
+                if (lane >= d) {
+                    rc += r2;
+                    cc += c2;
+                }
+            }
+            if (lane < MV) {
+                R.sj[lane] = moved ? sj : 0;
+                R.sm[lane] = moved ? m : 0;
+                R.roff[lane + 1] = rc;
+                R.coff[lane + 1] = cc;
+            }
+            if (lane == 63) {
+                R.rtot = rc;
+                R.ctot = cc;
+            }
+            if (lane == 0) {
+                R.roff[0] = 0;
+                R.coff[0] = 0;
+                const int nfin = __ffsll((long long)~finm) - 1;
+                R.head = head + min(nfin, nact);
+                if (stop) R.halt = 1;
+                S.nswap += __popcll(tried);
+            }
+            if (lane == nact && nact < MV && !halt0) {
+                R.ns = ns;
+                R.ilst = ilst;
+                R.chk_done = chk_done ? 1 : 0;
+                if (created) R.tail = tail + 1;
+            }
+        }
         __syncthreads();
-        return 1;
-    }
-    // rows j..j+m-1 over columns j+m..nt-1 (G^T from the left); columns over
-    // rows 0..j-1 and Z rows (G from the right): disjoint regions.
-    int ncl = nt - (j + m);
-    int total = max(ncl, 0) + j + nz;
-    for (int it = threadIdx.x; it < total; it += NT) {
-        double x[4], y[4];
-        if (it < ncl) {
-            int c = j + m + it;
+        const int rtot = R.rtot, ctot = R.ctot;
+        // left products: rows sj..sj+m-1 over the columns right of the range
+        {
+            int s = 0;
+            for (int it = tid; it < rtot; it += NT) {
+                while (it >= R.roff[s + 1]) ++s;
+                const int j = R.sj[s], m = R.sm[s];
+                const double *G = R.G + s * 16;
+                const int c = j + m + (it - R.roff[s]);
+                double x[4], y[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) x[r] = (r < m) ? T[(j + r) + c * ldt] : 0.0;
+                for (int r = 0; r < 4; ++r) x[r] = (r < m) ? T[(j + r) + c * ldt] : 0.0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                double acc = 0.0;
+                for (int r = 0; r < 4; ++r) {
+                    double acc = 0.0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (i < m && r < m) acc += S.G[i + m * r] * x[i];
-                y[r] = acc;
+                    for (int i = 0; i < 4; ++i)
+                        if (i < m && r < m) acc += G[i + m * r] * x[i];
+                    y[r] = acc;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r < m) T[(j + r) + c * ldt] = y[r];
             }
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (r < m) T[(j + r) + c * ldt] = y[r];
-        } else {
-            double *Mx;
-            int ld;
-            int rr = it - max(ncl, 0);
-            if (rr < j) {
-                Mx = T + rr;
-                ld = ldt;
-            } else {
-                Mx = Z + (rr - j);
-                ld = ldz;
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) x[c] = (c < m) ? Mx[(j + c) * ld] : 0.0;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                double acc = 0.0;
-#pragma unroll
-                for (int l = 0; l < 4; ++l)
-                    if (l < m && c < m) acc += x[l] * S.G[l + m * c];
-                y[c] = acc;
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (c < m) Mx[(j + c) * ld] = y[c];
         }
-    }
-    if (threadIdx.x < m * m) {
-        int r = threadIdx.x % m, c = threadIdx.x / m;
-        T[(j + r) + (j + c) * ldt] = S.Dn[r + 4 * c];
-    }
-    __syncthreads();
-    return 0;
-}
-
-// Move the block starting at ifst up to ilst.  Returns 0, or 1 when a swap was
-// rejected or a 2x2 block split (the reordering halts, Schur form stays valid).
-__device__ int move_block_up(SmemCore &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int ifst,
-                             int ilst, double smlnum)
-{
-    int here = ifst;
-    int sz = (here + 1 < nt && T[(here + 1) + here * ldt] != 0.0) ? 2 : 1;
-    while (here > ilst) {
-        int above = (here - 2 >= 0 && T[(here - 1) + (here - 2) * ldt] != 0.0) ? 2 : 1;
-        int j = here - above;
-        if (j < ilst) return 1;
-        if (swap_blocks(S, T, ldt, nt, Z, ldz, nz, j, above, sz, smlnum)) return 1;
-        here = j;
-        if (sz == 2 && T[(here + 1) + here * ldt] == 0.0) return 1;
-    }
-    return 0;
-}
-
-// Bottom-up deflation test of the candidates of the quasi-triangular T
-// (order nt) with spike entries sp_k = spscale * Z[sprow + k*ldz]; failures
-// move to the top.  Returns the number of undeflated leading rows.
-__device__ int aed_deflate(SmemCore &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int sprow,
-                           double spscale, int ilst, double smlnum)
-{
-    int ns = nt;
-    bool halted = false;
-    while (ilst < ns && !halted) {
-        bool two = (ns >= 2 && T[(ns - 1) + (ns - 2) * ldt] != 0.0);
-        if (two && ns - 2 < ilst) break;
-        int k = ns - 1;
-        bool defl;
-        if (!two) {
-            double foo = fabs(T[k + k * ldt]);
-            defl = fabs(spscale * Z[sprow + k * ldz]) <= fmax(smlnum, kU * foo);
-        } else {
-            double hh = sqrt(fabs(T[k + k * ldt] * T[(k - 1) + (k - 1) * ldt])) +
-                        sqrt(fabs(T[(k - 1) + k * ldt] * T[k + (k - 1) * ldt]));
-            double sp = fmax(fabs(spscale * Z[sprow + k * ldz]), fabs(spscale * Z[sprow + (k - 1) * ldz]));
-            defl = sp <= fmax(smlnum, kU * hh);
-        }
-        int sz = two ? 2 : 1;
         __syncthreads();
-        if (defl) {
-            ns -= sz;
-        } else {
-            int ifst = ns - sz;
-            if (ifst > ilst && move_block_up(S, T, ldt, nt, Z, ldz, nz, ifst, ilst, smlnum)) halted = true;
-            ilst += sz;
+        // right products: columns sj..sj+m-1 over the rows of T above the range and all rows of Z
+        {
+            int s = 0;
+            for (int it = tid; it < ctot; it += NT) {
+                while (it >= R.coff[s + 1]) ++s;
+                const int j = R.sj[s], m = R.sm[s];
+                const double *G = R.G + s * 16;
+                const int rr = it - R.coff[s];
+                double *Mx;
+                int ld;
+                if (rr < j) {
+                    Mx = T + rr;
+                    ld = ldt;
+                } else {
+                    Mx = Z + (rr - j);
+                    ld = ldz;
+                }
+                double x[4], y[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) x[c] = (c < m) ? Mx[(j + c) * ld] : 0.0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int l = 0; l < 4; ++l)
+                        if (l < m && c < m) acc += x[l] * G[l + m * c];
+                    y[c] = acc;
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (c < m) Mx[(j + c) * ld] = y[c];
+            }
         }
+        ++nphase;
+        if (tid == 0) {
+            S.nrphase += 1;
+            // every phase moves the oldest block or examines a candidate, so
+            // nt * nt phases bound the loop; the cap only guards that argument
+            if (R.halt || (R.chk_done && R.head == R.tail) || nphase >= nt * nt + 64) R.done = 1;
+        }
+        par ^= 1;
+        __syncthreads();
     }
+    const int ns = R.ns;
     __syncthreads();
     return ns;
 }
 
 // Householder vector of x = vec[0..len-1] (in LDS): overwrites vec with v
 // (v[0] = 1) and returns tau; beta in S.sc[2].
-__device__ double house_vec(Smem &S, double *vec, int len)
+__device__ __forceinline__ double house_vec(Smem &S, double *vec, int len)
 {
     double amax = 0.0;
     for (int i = 1 + (int)threadIdx.x; i < len; i += NT) amax = fmax(amax, fabs(vec[i]));
@@ -1234,7 +1304,7 @@ __device__ double house_vec(Smem &S, double *vec, int len)
 // Spike removal and Householder Hessenberg reduction of T(0:ns,0:ns) in LDS;
 // the reflectors also update T(0:ns, ns:nt) and Z (nz rows).  The spike is
 // spscale * Z[sprow, 0:ns] on entry.  Returns the new subdiagonal entry.
-__device__ double restore_lds(Smem &S, double *T, int ldt, int nt, int ns, double *Z, int ldz, int nz,
+__device__ __forceinline__ double restore_lds(Smem &S, double *T, int ldt, int nt, int ns, double *Z, int ldz, int nz,
                               int sprow, double spscale)
 {
     double *v = S.vec;
@@ -1294,7 +1364,7 @@ __device__ double restore_lds(Smem &S, double *T, int ldt, int nt, int ns, doubl
 }
 
 // Store Z^T (order m) zero padded to order K16 into Ut (column major, ld K16).
-__device__ void store_factor_t(const double *Z, int ldz, int m, double *Ut)
+__device__ __forceinline__ void store_factor_t(const double *Z, int ldz, int m, double *Ut)
 {
     int K16 = (m + 15) & ~15;
     for (int it = threadIdx.x; it < K16 * K16; it += NT) {
@@ -1303,7 +1373,7 @@ __device__ void store_factor_t(const double *Z, int ldz, int m, double *Ut)
     }
 }
 
-__device__ void identity_lds(double *Z, int ldz, int m, int rows)
+__device__ __forceinline__ void identity_lds(double *Z, int ldz, int m, int rows)
 {
     for (int it = threadIdx.x; it < rows * m; it += NT) {
         int r = it % rows, c = it / rows;
@@ -1368,6 +1438,7 @@ __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int i
     if (tid == 0) {
         S.ic[3] = ilo;
         S.flops = 0.0;
+        S.nphase = S.nbstep = S.nswap = S.nrphase = 0;
     }
     __syncthreads();
     for (int l = kbot - tid; l > ilo; l -= NT) {
@@ -1477,6 +1548,10 @@ __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int i
         st->info = small ? (info > 0 ? kw + info : 0) : 0;
         st->changed = changed ? 1 : 0;
         st->beta = S.flops;
+        st->nphase = S.nphase;
+        st->nbstep = S.nbstep;
+        st->nswap = S.nswap;
+        st->nrphase = S.nrphase;
         st->tick[0] = t_schur - t_start;
         st->tick[1] = t_defl - t_schur;
         st->tick[2] = t_rest - t_defl;
@@ -1547,6 +1622,7 @@ __global__ void __launch_bounds__(NT) k_corner_deflate(double *T, int64_t ldt, i
     }
     identity_lds(S.Z, LDM, wd, wd);
     for (int c = tid; c < wd; c += NT) S.Z[wd + c * LDM] = s * V[(int64_t)(c0 + c) * ldv];
+    if (tid == 0) S.nswap = S.nrphase = 0;
     __syncthreads();
     int nsc = aed_deflate(S, S.A, LDM, wd, S.Z, LDM, wd + 1, wd, 1.0, 0, smlnum);
     __syncthreads();
@@ -1814,6 +1890,7 @@ __global__ void k_transpose_pad(const double *V, int64_t ldv, int K, double *Ut,
 // ---------------------------------------------------------------------------
 // launchers
 
+static_assert(sizeof(Smem) <= 160 * 1024, "the LDS kernels need one workgroup's 160 KB of LDS at most");
 static size_t smem_bytes() { return sizeof(Smem); }
 
 static hipError_t prep(const void *fn)

@@ -32,11 +32,23 @@ def read() -> dict:
 
 def lds_split() -> dict:
     """Fractions of the LDS iteration kernel's device time spent in the Schur
-    solve, the reordering and the Hessenberg restoration."""
-    t = (ctypes.c_int64 * 4)()
-    lib().hqr_profile_ticks(t, 4)
+    solve, the reordering and the Hessenberg restoration, with the event
+    counts behind them (chase phases, single-bulge steps, swaps, launches of
+    each kind) and the device clock cycles per phase and per swap."""
+    t = (ctypes.c_int64 * 10)()
+    lib().hqr_profile_ticks(t, 10)
     tot = max(int(t[3]), 1)
-    return {"schur": t[0] / tot, "reorder": t[1] / tot, "restore": t[2] / tot}
+    out = {"schur": t[0] / tot, "reorder": t[1] / tot, "restore": t[2] / tot,
+           "phases": int(t[4]), "bulge_steps": int(t[5]), "swaps": int(t[6]),
+           "small_launches": int(t[7]), "aed_launches": int(t[8]), "reorder_phases": int(t[9])}
+    # wall clock at 100 MHz, shader clock 2.4 GHz
+    if t[4] > 0:
+        out["us_per_phase"] = t[0] / 100.0 / t[4]
+    if t[6] > 0:
+        out["us_per_swap"] = t[1] / 100.0 / t[6]
+    if t[9] > 0:
+        out["us_per_reorder_phase"] = t[1] / 100.0 / t[9]
+    return out
 
 
 def summary(prof: dict, steps: int) -> dict:
