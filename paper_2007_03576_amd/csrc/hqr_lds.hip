@@ -81,6 +81,34 @@ __device__ inline void house3(int m, double x0, double x1, double x2, double &v1
     beta = b;
 }
 
+// house3 with one square root and no scaling when every entry lies well
+// inside the range where squaring neither overflows nor underflows (the
+// usual case); otherwise the scaled form above.
+__device__ inline void house3f(int m, double x0, double x1, double x2, double &v1, double &v2, double &tau,
+                               double &beta)
+{
+    const double t1 = (m > 1) ? x1 : 0.0, t2 = (m > 2) ? x2 : 0.0;
+    if (t1 == 0.0 && t2 == 0.0) {
+        tau = 0.0;
+        beta = x0;
+        v1 = v2 = 0.0;
+        return;
+    }
+    const double amax = fmax(fabs(x0), fmax(fabs(t1), fabs(t2)));
+    if (!(amax > 0x1p-450 && amax < 0x1p+450)) {
+        house3(m, x0, x1, x2, v1, v2, tau, beta);
+        return;
+    }
+    const double nrm = sqrt(fma(x0, x0, fma(t1, t1, t2 * t2)));
+    const double b = (x0 >= 0.0) ? -nrm : nrm;
+    const double d = x0 - b; // |d| = |x0| + nrm
+    const double rd = 1.0 / d;
+    tau = -d / b;
+    v1 = t1 * rd;
+    v2 = t2 * rd;
+    beta = b;
+}
+
 // Ahues-Tisseur small-subdiagonal test of A[k,k-1] inside [lo,hi].
 __device__ inline bool small_sub(const double *A, int lda, int k, int lo, int hi, double smlnum)
 {
@@ -468,6 +496,167 @@ __device__ __forceinline__ void chain_chase(SmemCore &S, double *A, int lda, int
     if (tid == 0) S.flops += fl;
 }
 
+// Single-bulge chase (one double-shift sweep) through the matrix held in LDS:
+// the reflector at k acts on rows/columns k+1..k+m of the active block
+// [ktop,kbot] (indices global, local = global - off), left products on local
+// columns up to colhi, right products on local rows 0..k+4 and on the nz rows
+// of Z.  One barrier per step.  Every thread computes the reflector itself;
+// the entries a thread updates are loaded before the reflector is formed, so
+// their latency hides behind it.  The item of one thread is a column segment
+// (left product), a row segment (right product) or, for one thread, the 3x3
+// block on the diagonal (both products); the new bulge column is written one
+// step later, when nobody reads it.
+__device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off, int ktop, int kbot, int p0,
+                                       int nsteps, int kend, int colhi, double *Z, int ldz, int nz)
+{
+    const int tid = threadIdx.x;
+    const int kbl = kbot - off;
+    int pend_kl = -1, pend_m = 0;
+    double pend_beta = 0.0;
+    double fl = 0.0;
+    for (int t = 0; t < nsteps; ++t) {
+        const int k = p0 + t;
+        if (k < ktop - 1 || k > kend) continue;
+        const int kl = k - off;
+        const int m = min(3, kbot - k);
+        const bool intro = (k == ktop - 1);
+        const int c0L = kl + m + 1;
+        const int ncL = max(0, colhi - c0L + 1);
+        const int nrR = kl + 1;
+        const bool extra = (m == 3 && kl + 4 <= kbl);
+        const int perR = nrR + nz + (extra ? 1 : 0);
+        const int own = ncL + perR;
+        const int total = own + 1;
+        // entries of this thread's first item, loaded before the reflector
+        double *p = A;
+        int st = 0;
+        double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+        double B00 = 0.0, B01 = 0.0, B02 = 0.0, B10 = 0.0, B11 = 0.0, B12 = 0.0, B20 = 0.0, B21 = 0.0, B22 = 0.0;
+        double *a = A + (kl + 1) + (kl + 1) * lda;
+        const int it = tid;
+        if (it < own) {
+            if (it < ncL) {
+                p = A + (c0L + it) * lda + (kl + 1);
+                st = 1;
+            } else {
+                const int r = it - ncL;
+                if (r < nrR) {
+                    p = A + r + (kl + 1) * lda;
+                    st = lda;
+                } else if (r < nrR + nz) {
+                    p = Z + (r - nrR) + (kl + 1) * ldz;
+                    st = ldz;
+                } else {
+                    p = A + (kl + 4) + (kl + 1) * lda;
+                    st = lda;
+                }
+            }
+            y0 = p[0];
+            y1 = p[st];
+            if (m == 3) y2 = p[2 * st];
+        } else if (it == own) {
+            B00 = a[0];
+            B10 = a[1];
+            B01 = a[lda];
+            B11 = a[1 + lda];
+            if (m == 3) {
+                B02 = a[2 * lda];
+                B12 = a[1 + 2 * lda];
+                B20 = a[2];
+                B21 = a[2 + lda];
+                B22 = a[2 + 2 * lda];
+            }
+        }
+        double x0, x1, x2;
+        if (intro) {
+            shift_column(A, lda, kl + 1, kbl, S.sr[0], S.si[0], S.sr[1], S.si[1], x0, x1, x2);
+            __syncthreads(); // the leading block is read before anyone overwrites it
+        } else {
+            x0 = A[(kl + 1) + kl * lda];
+            x1 = A[(kl + 2) + kl * lda];
+            x2 = (m == 3) ? A[(kl + 3) + kl * lda] : 0.0;
+        }
+        double v1, v2, tau, beta;
+        house3f(m, x0, x1, x2, v1, v2, tau, beta);
+        if (m < 3) v2 = 0.0;
+        if (tau != 0.0) {
+            if (it < own) {
+                refl3(m, tau, v1, v2, y0, y1, y2);
+                p[0] = y0;
+                p[st] = y1;
+                if (m == 3) p[2 * st] = y2;
+            } else if (it == own) {
+                refl3(3, tau, v1, v2, B00, B10, B20);
+                refl3(3, tau, v1, v2, B01, B11, B21);
+                refl3(3, tau, v1, v2, B02, B12, B22);
+                refl3(3, tau, v1, v2, B00, B01, B02);
+                refl3(3, tau, v1, v2, B10, B11, B12);
+                refl3(3, tau, v1, v2, B20, B21, B22);
+                a[0] = B00;
+                a[1] = B10;
+                a[lda] = B01;
+                a[1 + lda] = B11;
+                if (m == 3) {
+                    a[2] = B20;
+                    a[2 + lda] = B21;
+                    a[2 * lda] = B02;
+                    a[1 + 2 * lda] = B12;
+                    a[2 + 2 * lda] = B22;
+                }
+            }
+            // further items (matrices with more rows than threads)
+            for (int it2 = tid + NT; it2 < own; it2 += NT) {
+                double *q;
+                int sq;
+                if (it2 < ncL) {
+                    q = A + (c0L + it2) * lda + (kl + 1);
+                    sq = 1;
+                } else {
+                    const int r = it2 - ncL;
+                    if (r < nrR) {
+                        q = A + r + (kl + 1) * lda;
+                        sq = lda;
+                    } else if (r < nrR + nz) {
+                        q = Z + (r - nrR) + (kl + 1) * ldz;
+                        sq = ldz;
+                    } else {
+                        q = A + (kl + 4) + (kl + 1) * lda;
+                        sq = lda;
+                    }
+                }
+                double z0 = q[0], z1 = q[sq], z2 = (m == 3) ? q[2 * sq] : 0.0;
+                refl3(m, tau, v1, v2, z0, z1, z2);
+                q[0] = z0;
+                q[sq] = z1;
+                if (m == 3) q[2 * sq] = z2;
+            }
+        }
+        if (tid == 0) {
+            if (pend_m > 0) {
+                A[(pend_kl + 1) + pend_kl * lda] = pend_beta;
+                A[(pend_kl + 2) + pend_kl * lda] = 0.0;
+                if (pend_m == 3) A[(pend_kl + 3) + pend_kl * lda] = 0.0;
+            }
+            pend_m = intro ? 0 : m;
+            pend_kl = kl;
+            pend_beta = beta;
+            fl += 4.0 * 3.0 * (double)(total - 1) + 40.0;
+            S.nphase += 1;
+            S.nbstep += 1;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (pend_m > 0) {
+            A[(pend_kl + 1) + pend_kl * lda] = pend_beta;
+            A[(pend_kl + 2) + pend_kl * lda] = 0.0;
+            if (pend_m == 3) A[(pend_kl + 3) + pend_kl * lda] = 0.0;
+        }
+        S.flops += fl;
+    }
+    __syncthreads();
+}
+
 // Largest l in (lo,hi] whose subdiagonal A[l,l-1] is zero or negligible
 // (then set to zero); lo if there is none.
 __device__ __forceinline__ int find_split(SmemCore &S, double *A, int lda, int lo, int hi, double smlnum)
@@ -583,7 +772,7 @@ __device__ __forceinline__ void ds_step(SmemCore &S, double *A, int lda, int m, 
         S.si[1] = i2;
     }
     __syncthreads();
-    chain_chase(S, A, lda, 0, l, i, l - 1, (i - 2) - (l - 1) + 1, i - 2, 1, m - 1, Z, ldz, nz);
+    chase1(S, A, lda, 0, l, i, l - 1, (i - 2) - (l - 1) + 1, i - 2, m - 1, Z, ldz, nz);
 }
 
 // Francis double-shift QR on the whole matrix A (order m, full T), Z accumulates.
@@ -645,7 +834,7 @@ __device__ __forceinline__ int qr_small(SmemCore &S, double *A, int lda, int m, 
                     S.shb[r + c * ns] = (r <= c + 1) ? A[(j0 + r) + (j0 + c) * lda] : 0.0;
                 }
                 __syncthreads();
-                int inf = qr_ds(S, S.shb, ns, ns, nullptr, 0, 0, smlnum, 0);
+                int inf = qr_ds(S, S.shb, ns, ns, S.shb, ns, 0, smlnum, 0); // no Z rows (nz = 0)
                 if (threadIdx.x == 0) {
                     // pair the eigenvalues of the converged part, bottom first
                     int cnt = 0;
@@ -2093,10 +2282,10 @@ __global__ void __launch_bounds__(NT) k_batched_global(double *H, double *Q, con
             int r = it % n, c = it / n;
             if (r > c + 1) A[it] = 0.0;
         }
-        double *Z = Q ? Q + offs[b] : nullptr;
+        double *Z = Q ? Q + offs[b] : A; // without Q: no Z rows (nz = 0)
         __syncthreads();
         const double smlnum = DBL_MIN * ((double)n / kU);
-        int inf = qr_small(S, A, n, n, Z, n, Z ? n : 0, smlnum, 0, nsmall);
+        int inf = qr_small(S, A, n, n, Z, n, Q ? n : 0, smlnum, 0, nsmall);
         __syncthreads();
         if (tid == 0) {
             double *er = wr + eoff[b], *ei = wi + eoff[b];
