@@ -511,7 +511,7 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
 {
     const int tid = threadIdx.x;
     const int kbl = kbot - off;
-    int pend_kl = -1, pend_m = 0;
+    int pend_kl = -1, pend_m = 0, nph = 0;
     double pend_beta = 0.0;
     double fl = 0.0;
     for (int t = 0; t < nsteps; ++t) {
@@ -525,36 +525,28 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
         const int nrR = kl + 1;
         const bool extra = (m == 3 && kl + 4 <= kbl);
         const int perR = nrR + nz + (extra ? 1 : 0);
-        const int own = ncL + perR;
-        const int total = own + 1;
-        // entries of this thread's first item, loaded before the reflector
-        double *p = A;
-        int st = 0;
-        double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+        const int own = ncL + perR;  // number of row/column segments
+        const int total = own + 1;     // and the diagonal block
+        // the diagonal block goes to thread ownidx, the segments to the other
+        // threads in order, then round-robin over all threads
+        const int ownidx = min(own, NT - 1);
+        const bool mine = (tid == ownidx);
+        const int it = (tid < ownidx) ? tid : tid - 1;
+        const bool seg = !mine && it < own;
+        double sx0 = 0.0, sx1 = 0.0, sx2 = 0.0;
+        if (intro) {
+            shift_column(A, lda, kl + 1, kbl, S.sr[0], S.si[0], S.sr[1], S.si[1], sx0, sx1, sx2);
+            __syncthreads(); // the leading block is read before anyone overwrites it
+        }
+        // Loads in the order the data is needed: the diagonal block (one
+        // thread), the bulge column, then this thread's segment.  The column
+        // and segment loads are unconditional (a harmless in-bounds address
+        // where there is nothing to load) so that waiting for the column does
+        // not wait for the segment, whose latency then hides behind the
+        // reflector.
         double B00 = 0.0, B01 = 0.0, B02 = 0.0, B10 = 0.0, B11 = 0.0, B12 = 0.0, B20 = 0.0, B21 = 0.0, B22 = 0.0;
         double *a = A + (kl + 1) + (kl + 1) * lda;
-        const int it = tid;
-        if (it < own) {
-            if (it < ncL) {
-                p = A + (c0L + it) * lda + (kl + 1);
-                st = 1;
-            } else {
-                const int r = it - ncL;
-                if (r < nrR) {
-                    p = A + r + (kl + 1) * lda;
-                    st = lda;
-                } else if (r < nrR + nz) {
-                    p = Z + (r - nrR) + (kl + 1) * ldz;
-                    st = ldz;
-                } else {
-                    p = A + (kl + 4) + (kl + 1) * lda;
-                    st = lda;
-                }
-            }
-            y0 = p[0];
-            y1 = p[st];
-            if (m == 3) y2 = p[2 * st];
-        } else if (it == own) {
+        if (mine) {
             B00 = a[0];
             B10 = a[1];
             B01 = a[lda];
@@ -567,25 +559,38 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
                 B22 = a[2 + 2 * lda];
             }
         }
-        double x0, x1, x2;
+        const double *xc = A + (kl + 1) + max(kl, 0) * lda;
+        double x0 = xc[0], x1 = xc[1], x2 = xc[(m == 3) ? 2 : 1];
+        // segment geometry without branches: column segment (left product),
+        // row of A above the block, row of Z, or row kl+4 (right product)
+        const int r = it - ncL;
+        const bool isL = it < ncL, isA = !isL && r < nrR, isZ = !isL && !isA && r < nrR + nz;
+        double *base = isZ ? Z : A;
+        const int ldb = isZ ? ldz : lda;
+        const int prow = !seg ? 0 : (isL ? (kl + 1) : (isA ? r : (isZ ? r - nrR : kl + 4)));
+        const int pcol = !seg ? 0 : (isL ? (c0L + it) : (kl + 1));
+        const int st = (!seg || isL) ? 1 : ldb;
+        double *p = base + prow + pcol * ldb;
+        double y0 = p[0], y1 = p[st], y2 = p[((m == 3) ? 2 : 1) * st];
         if (intro) {
-            shift_column(A, lda, kl + 1, kbl, S.sr[0], S.si[0], S.sr[1], S.si[1], x0, x1, x2);
-            __syncthreads(); // the leading block is read before anyone overwrites it
-        } else {
-            x0 = A[(kl + 1) + kl * lda];
-            x1 = A[(kl + 2) + kl * lda];
-            x2 = (m == 3) ? A[(kl + 3) + kl * lda] : 0.0;
+            x0 = sx0;
+            x1 = sx1;
+            x2 = sx2;
+        }
+        if (m < 3) {
+            x2 = 0.0;
+            y2 = 0.0;
         }
         double v1, v2, tau, beta;
         house3f(m, x0, x1, x2, v1, v2, tau, beta);
         if (m < 3) v2 = 0.0;
         if (tau != 0.0) {
-            if (it < own) {
+            if (seg) {
                 refl3(m, tau, v1, v2, y0, y1, y2);
                 p[0] = y0;
                 p[st] = y1;
                 if (m == 3) p[2 * st] = y2;
-            } else if (it == own) {
+            } else if (mine) {
                 refl3(3, tau, v1, v2, B00, B10, B20);
                 refl3(3, tau, v1, v2, B01, B11, B21);
                 refl3(3, tau, v1, v2, B02, B12, B22);
@@ -605,7 +610,7 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
                 }
             }
             // further items (matrices with more rows than threads)
-            for (int it2 = tid + NT; it2 < own; it2 += NT) {
+            for (int it2 = tid + NT - 1; it2 < own; it2 += NT) {
                 double *q;
                 int sq;
                 if (it2 < ncL) {
@@ -641,8 +646,7 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
             pend_kl = kl;
             pend_beta = beta;
             fl += 4.0 * 3.0 * (double)(total - 1) + 40.0;
-            S.nphase += 1;
-            S.nbstep += 1;
+            ++nph;
         }
         __syncthreads();
     }
@@ -653,8 +657,179 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
             if (pend_m == 3) A[(pend_kl + 3) + pend_kl * lda] = 0.0;
         }
         S.flops += fl;
+        S.nphase += nph;
+        S.nbstep += nph;
     }
     __syncthreads();
+}
+
+// Single-bulge sweep (one Francis double-shift step) over the active block
+// [kt,kb] of the matrix in LDS (local indices), left products on columns up
+// to colhi, right products on rows 0..k+4 and on the nz rows of Z, done in
+// super-steps of SS bulge positions with two barriers each instead of one
+// barrier per position.
+//
+// The entries that the SS reflectors of a super-step at positions k0..k0+SS-1
+// both create and consume lie in the (SS+3) x (SS+3) window rows k0+1..k0+SS+3,
+// columns k0..k0+SS+2.  Every thread loads that window into registers and runs
+// the SS reflector steps on it itself (the reflectors never leave the
+// registers); the rest of the super-step's work is independent row and
+// column segments outside the window (SS+2 entries each: a column right of
+// the window for the left products, a row above it or a row of Z for the
+// right products), each owned by one thread that applies the SS reflectors in
+// order.  The window is written back by all threads, a few entries each.  The
+// first barrier keeps the write-back behind every thread's window load.
+static_assert(NT == 256, "the window write-back assumes four waves");
+template <int SS>
+__device__ __forceinline__ void chase_ws(SmemCore &S, double *A, int lda, int kt, int kb, int colhi, double *Z,
+                                         int ldz, int nz)
+{
+    constexpr int WR = SS + 3;
+    const int tid = threadIdx.x;
+    const int kfirst = kt - 1, klast = kb - 2;
+    const double sr0 = S.sr[0], si0 = S.si[0], sr1 = S.sr[1], si1 = S.si[1];
+    double fl = 0.0;
+    int nph = 0;
+    for (int k0 = kfirst; k0 <= klast; k0 += SS) {
+        const int R0 = k0 + 1;
+        const int nst = min(SS, klast - k0 + 1);
+        const int rlast = min(k0 + SS + 3, kb), clast = min(k0 + SS + 2, kb);
+        const int ccmin = (k0 == kfirst) ? 1 : 0; // column k0 lies outside the block at the introduction
+        // this thread's segment: a column right of the window (left products),
+        // a row above it, or a row of Z (right products)
+        const int ncL = max(0, colhi - clast), nrR = R0;
+        const int nseg = ncL + nrR + nz;
+        const int it = tid;
+        const bool seg = it < nseg;
+        const bool isL = it < ncL, isA = !isL && it - ncL < nrR;
+        double *base = (seg && !isL && !isA) ? Z : A;
+        const int ldb = (seg && !isL && !isA) ? ldz : lda;
+        // first entry and stride; nvalid entries exist (rows / columns <= kb)
+        const int prow = !seg ? 0 : (isL ? R0 : (isA ? it - ncL : it - ncL - nrR));
+        const int pcol = !seg ? 0 : (isL ? clast + 1 + it : R0);
+        const int st = (!seg || isL) ? 1 : ldb;
+        const int nvalid = !seg ? 0 : min(SS + 2, kb - R0 + 1);
+        double *p = base + prow + pcol * ldb;
+        double y[SS + 2];
+#pragma unroll
+        for (int j = 0; j < SS + 2; ++j) y[j] = (j < nvalid) ? p[j * st] : 0.0;
+        // the window
+        double W[WR][WR];
+#pragma unroll
+        for (int cc = 0; cc < WR; ++cc)
+#pragma unroll
+            for (int rr = 0; rr < WR; ++rr)
+                W[rr][cc] = (cc >= ccmin && k0 + cc <= clast && R0 + rr <= rlast)
+                                ? A[(R0 + rr) + (k0 + cc) * lda]
+                                : 0.0;
+        __syncthreads(); // every thread holds the window before anyone writes it back
+        double rv1[SS], rv2[SS], rtau[SS];
+        int rm[SS];
+#pragma unroll
+        for (int i = 0; i < SS; ++i) {
+            rtau[i] = 0.0;
+            rv1[i] = rv2[i] = 0.0;
+            rm[i] = 0;
+            if (i < nst) {
+                const int kl = k0 + i;
+                const int m = min(3, kb - kl);
+                double x0, x1, x2;
+                if (kl == kfirst) {
+                    // introduction (i = 0): first column of the shift polynomial
+                    const double h11 = W[0][1], h21 = W[1][1], h12 = W[0][2], h22 = W[1][2];
+                    const double h32 = (kt + 2 <= kb) ? W[2][2] : 0.0;
+                    const double sc = fabs(h11 - sr1) + fabs(si1) + fabs(h21);
+                    if (sc == 0.0) {
+                        x0 = x1 = x2 = 0.0;
+                    } else {
+                        const double f = h21 / sc;
+                        x0 = f * h12 + (h11 - sr0) * ((h11 - sr1) / sc) - si0 * (si1 / sc);
+                        x1 = f * (h11 + h22 - sr0 - sr1);
+                        x2 = f * h32;
+                    }
+                } else {
+                    x0 = W[i][i];
+                    x1 = W[i + 1][i];
+                    x2 = (m == 3) ? W[i + 2][i] : 0.0;
+                }
+                double v1, v2, tau, beta;
+                house3f(m, x0, x1, x2, v1, v2, tau, beta);
+                if (m < 3) v2 = 0.0;
+                rv1[i] = v1;
+                rv2[i] = v2;
+                rtau[i] = tau;
+                rm[i] = m;
+                if (tau != 0.0) {
+                    // left product on window rows i..i+m-1, columns right of the bulge column
+#pragma unroll
+                    for (int cc = i + 1; cc < WR; ++cc)
+                        refl3(m, tau, v1, v2, W[i][cc], W[i + 1][cc], W[i + 2][cc]);
+                    // right product on window columns i+1..i+m, rows 0..i+3
+#pragma unroll
+                    for (int rr = 0; rr <= i + 3; ++rr)
+                        refl3(m, tau, v1, v2, W[rr][i + 1], W[rr][i + 2], W[rr][i + 3]);
+                }
+                if (kl != kfirst) {
+                    W[i][i] = beta;
+                    W[i + 1][i] = 0.0;
+                    if (m == 3) W[i + 2][i] = 0.0;
+                }
+            }
+        }
+        // the thread's segment
+        if (seg) {
+#pragma unroll
+            for (int i = 0; i < SS; ++i)
+                if (rtau[i] != 0.0) refl3(rm[i], rtau[i], rv1[i], rv2[i], y[i], y[i + 1], y[i + 2]);
+#pragma unroll
+            for (int j = 0; j < SS + 2; ++j)
+                if (j < nvalid) p[j * st] = y[j];
+        }
+        // segments beyond the first NT (matrices with more rows than threads)
+        for (int it2 = tid + NT; it2 < nseg; it2 += NT) {
+            const bool L2 = it2 < ncL, A2 = !L2 && it2 - ncL < nrR;
+            double *q = (!L2 && !A2) ? Z : A;
+            const int ld2 = (!L2 && !A2) ? ldz : lda;
+            const int qr = L2 ? R0 : (A2 ? it2 - ncL : it2 - ncL - nrR);
+            const int qc = L2 ? clast + 1 + it2 : R0;
+            const int s2 = L2 ? 1 : ld2;
+            q += qr + qc * ld2;
+            double u[SS + 2];
+#pragma unroll
+            for (int j = 0; j < SS + 2; ++j) u[j] = (j < nvalid) ? q[j * s2] : 0.0;
+#pragma unroll
+            for (int i = 0; i < SS; ++i)
+                if (rtau[i] != 0.0) refl3(rm[i], rtau[i], rv1[i], rv2[i], u[i], u[i + 1], u[i + 2]);
+#pragma unroll
+            for (int j = 0; j < SS + 2; ++j)
+                if (j < nvalid) q[j * s2] = u[j];
+        }
+        // write the window back: lane 0 of wave w stores the entries f with
+        // f = w (mod 4); every thread holds the same window
+        if ((tid & 63) == 0) {
+            const int w = tid >> 6;
+#pragma unroll
+            for (int f = 0; f < WR * WR; ++f) {
+                const int rr = f % WR, cc = f / WR;
+                if ((f & 3) == w && cc >= ccmin && k0 + cc <= clast && R0 + rr <= rlast)
+                    A[(R0 + rr) + (k0 + cc) * lda] = W[rr][cc];
+            }
+        }
+        if (tid == 0) {
+            for (int i = 0; i < nst; ++i) {
+                const int kl = k0 + i, m = min(3, kb - kl);
+                const int extra = (m == 3 && kl + 4 <= kb) ? 1 : 0;
+                fl += 12.0 * (double)(max(0, colhi - kl - m) + kl + 1 + nz + extra) + 40.0;
+            }
+            nph += 1;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        S.flops += fl;
+        S.nphase += nph;
+        S.nbstep += kb - kt;
+    }
 }
 
 // Largest l in (lo,hi] whose subdiagonal A[l,l-1] is zero or negligible
@@ -772,7 +947,7 @@ __device__ __forceinline__ void ds_step(SmemCore &S, double *A, int lda, int m, 
         S.si[1] = i2;
     }
     __syncthreads();
-    chase1(S, A, lda, 0, l, i, l - 1, (i - 2) - (l - 1) + 1, i - 2, m - 1, Z, ldz, nz);
+    chase_ws<4>(S, A, lda, l, i, m - 1, Z, ldz, nz);
 }
 
 // Francis double-shift QR on the whole matrix A (order m, full T), Z accumulates.
