@@ -45,7 +45,10 @@ extern "C" {
  *              active block and to Q on a second stream (Sec. 3.3 priorities)
  *   small_shifts  shifts per sweep of the one-workgroup solver (2 = Francis
  *              double shift; 4..16 = chains of bulges shifted by the
- *              eigenvalues of the trailing block, Sec. 2.3) */
+ *              eigenvalues of the trailing block, Sec. 2.3)
+ *   aed_ns, aed_nw, aed_nmin  ns, nw and nmin of the recursive solve that
+ *              reduces an AED window larger than the one-workgroup solver
+ *              (the AED reduce state of Sec. 3.3); nw is capped at 96 */
 typedef struct hqr_params {
     int ns, nw, nmin, nibble, kexsh;
     int64_t itmax;
@@ -54,6 +57,7 @@ typedef struct hqr_params {
     double defl_thold;
     int streams;
     int small_shifts;
+    int aed_ns, aed_nw, aed_nmin;
 } hqr_params;
 
 /* Process-wide defaults used by later calls.  Returns 0 or -1 (NULL / invalid). */

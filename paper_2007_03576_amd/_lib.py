@@ -19,7 +19,8 @@ class HqrParams(ctypes.Structure):
                 ("nibble", ctypes.c_int), ("kexsh", ctypes.c_int), ("itmax", ctypes.c_int64),
                 ("window", ctypes.c_int), ("bulges_per_window", ctypes.c_int),
                 ("defl_mode", ctypes.c_int), ("defl_thold", ctypes.c_double),
-                ("streams", ctypes.c_int), ("small_shifts", ctypes.c_int)]
+                ("streams", ctypes.c_int), ("small_shifts", ctypes.c_int),
+                ("aed_ns", ctypes.c_int), ("aed_nw", ctypes.c_int), ("aed_nmin", ctypes.c_int)]
 
 
 EXPORTS = ["hqr_set_params", "hqr_get_params", "hqr_schur", "hqr_schur_ex", "hqr_schur_batched",

@@ -96,7 +96,8 @@ hipError_t launch_chase(double *H, int64_t ld, const ChaseRound &r, const double
 // Deflation check of the bottom corner of a large AED window (T in global
 // memory, order nw; the corner has order wd <= MMAX) with reordering.
 hipError_t launch_corner_deflate(double *T, int64_t ldt, int nw, int wd, const double *V, int64_t ldv,
-                                 double s, double smlnum, double *Ut, IterStatus *st, hipStream_t stream);
+                                 double s, double smlnum, double *Ut, IterStatus *st, int nforced,
+                                 hipStream_t stream);
 // Hessenberg restoration of T(0:ns,0:ns) in global memory with the spike,
 // applied to T(0:ns, ns:nw) and to V (rows 0..nv-1).
 hipError_t launch_restore(double *T, int64_t ldt, int nw, int ns, double *V, int64_t ldv, int nv,

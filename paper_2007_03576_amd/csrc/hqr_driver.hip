@@ -38,6 +38,7 @@ struct Params {
     int window, gsize;
     int streams;
     int nsmall; // shifts per multishift sweep of the one-workgroup solver (2 = double shift)
+    int aed_ns, aed_nw, aed_nmin; // recursive solve of large AED windows (0 = automatic)
 };
 
 // Reading of automatic parameters: LAPACK's documented shift-count table and
@@ -553,9 +554,16 @@ int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd
     }
     double *T = W.wT[depth], *Vw = W.wV[depth], *Ut = W.wU[depth];
     CK(launch_window_copy(V.H, V.ld, kwtop, w, T, w, Vw, w, C.hi));
+    // Reading for the recursive solve of the window: AED windows of w/4
+    // (48..96, within the one-workgroup solver) with nw/4 shifts per sweep;
+    // the one-workgroup AED steps then converge the window with few sweeps.
     Params Pi = C.P;
     auto_ns_nw(w, Pi.ns, Pi.nw);
-    Pi.nw = std::min(std::max(Pi.nw, 48), MMAX);
+    Pi.nw = std::min(std::max(w / 4, 48), MMAX);
+    Pi.ns = std::max(2, std::min(Pi.ns, (Pi.nw / 4) & ~1));
+    if (C.P.aed_nw > 0) Pi.nw = C.P.aed_nw;
+    if (C.P.aed_ns > 0) Pi.ns = C.P.aed_ns;
+    if (C.P.aed_nmin > 0) Pi.nmin = C.P.aed_nmin;
     Pi.ns = std::min(Pi.ns, std::max(2, (w / 4) & ~1));
     Pi.itmax = C.P.itmax;
     View Vi{T, w, w, Vw, w, w};
@@ -572,22 +580,40 @@ int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd
         ncand = w;
         return 0;
     }
-    int wd = std::min(w, MMAX);
-    int slc = take_slot(C);
-    double *Utc = slot_ptr(W, slc); // used on the critical stream only
-    int pidc = prof_begin(3, C.hi);
-    CK(launch_corner_deflate(T, w, w, wd, Vw, w, s, C.smlnum, Utc, W.st_dev, C.hi));
-    prof_end(pidc, C.hi, 0.0, 0.0);
-    if (read_status(C, 0)) return -1;
-    int c0 = W.st_host->kwtop, wdd = W.st_host->nw;
-    ns = W.st_host->ns;
-    nd = W.st_host->nd;
-    {
-        UpdBatch b = make_batch();
-        add_job(b, T + (int64_t)c0 * w, w, c0, wdd, Utc, 0);
-        add_job(b, Vw + (int64_t)c0 * w, w, w, wdd, Utc, 0);
-        if (flush(b, C.hi, C)) return -1;
+    // Deflation check of the whole window by a chain of deflation windows of
+    // order <= 96 moving up from the bottom corner (Sec. 3.3, deflate tasks):
+    // each window examines its unchecked candidates bottom-up, with the
+    // failures of the windows below it (at its bottom) treated as failed,
+    // and leaves all failures at its top; the next window ends at the
+    // bottommost failure.  The transformation of each window updates the
+    // window rows to its right, the rows above it and V.  The chain stops at
+    // the top of the AED window, after a rejected swap, or when the failures
+    // fill more than half of a window (the rest counts as undeflated).
+    int bot = w, nfail = 0;
+    for (;;) {
+        int wd = std::min(bot, MMAX);
+        if (wd <= nfail) break;
+        int slc = take_slot(C);
+        double *Utc = slot_ptr(W, slc); // used on the critical stream only
+        int pidc = prof_begin(3, C.hi);
+        CK(launch_corner_deflate(T, w, bot, wd, Vw, w, s, C.smlnum, Utc, W.st_dev, nfail, C.hi));
+        prof_end(pidc, C.hi, 0.0, 0.0);
+        if (read_status(C, 0)) return -1;
+        const int c0 = W.st_host->kwtop, wdd = W.st_host->nw, halted = W.st_host->info;
+        const int nsr = W.st_host->ns; // undeflated leading rows of the AED window
+        {
+            UpdBatch b = make_batch();
+            add_job(b, T + (int64_t)c0 * w, w, c0, wdd, Utc, 0);
+            add_job(b, T + c0 + (int64_t)bot * w, w, w - bot, wdd, Utc, 1);
+            add_job(b, Vw + (int64_t)c0 * w, w, w, wdd, Utc, 0);
+            if (flush(b, C.hi, C)) return -1;
+        }
+        nfail = nsr - c0;
+        bot = nsr;
+        if (halted || c0 == 0 || 2 * nfail > wdd) break;
     }
+    ns = bot;
+    nd = w - bot;
     CK(launch_block_eigs(T, w, ns, W.st_dev->cr, W.st_dev->ci, C.hi));
     ncand = ns;
     if (nd > 0) {
@@ -834,6 +860,9 @@ Params resolve(const hqr_params *pp, int n)
     P.gsize = p.bulges_per_window > 0 ? std::min(p.bulges_per_window, GMAX) : GMAX;
     P.streams = p.streams > 0 ? p.streams : 2;
     P.nsmall = p.small_shifts > 0 ? std::min(p.small_shifts, 16) & ~1 : 2;
+    P.aed_ns = p.aed_ns > 0 ? std::max(2, p.aed_ns & ~1) : 0;
+    P.aed_nw = p.aed_nw > 0 ? std::max(4, std::min(p.aed_nw, MMAX)) : 0;
+    P.aed_nmin = p.aed_nmin > 0 ? std::max(12, std::min(p.aed_nmin, MMAX)) : 0;
     if (P.nw < 2) P.nw = 2;
     return P;
 }

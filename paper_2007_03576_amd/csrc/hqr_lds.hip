@@ -663,175 +663,6 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
     __syncthreads();
 }
 
-// Single-bulge sweep (one Francis double-shift step) over the active block
-// [kt,kb] of the matrix in LDS (local indices), left products on columns up
-// to colhi, right products on rows 0..k+4 and on the nz rows of Z, done in
-// super-steps of SS bulge positions with two barriers each instead of one
-// barrier per position.
-//
-// The entries that the SS reflectors of a super-step at positions k0..k0+SS-1
-// both create and consume lie in the (SS+3) x (SS+3) window rows k0+1..k0+SS+3,
-// columns k0..k0+SS+2.  Every thread loads that window into registers and runs
-// the SS reflector steps on it itself (the reflectors never leave the
-// registers); the rest of the super-step's work is independent row and
-// column segments outside the window (SS+2 entries each: a column right of
-// the window for the left products, a row above it or a row of Z for the
-// right products), each owned by one thread that applies the SS reflectors in
-// order.  The window is written back by all threads, a few entries each.  The
-// first barrier keeps the write-back behind every thread's window load.
-static_assert(NT == 256, "the window write-back assumes four waves");
-template <int SS>
-__device__ __forceinline__ void chase_ws(SmemCore &S, double *A, int lda, int kt, int kb, int colhi, double *Z,
-                                         int ldz, int nz)
-{
-    constexpr int WR = SS + 3;
-    const int tid = threadIdx.x;
-    const int kfirst = kt - 1, klast = kb - 2;
-    const double sr0 = S.sr[0], si0 = S.si[0], sr1 = S.sr[1], si1 = S.si[1];
-    double fl = 0.0;
-    int nph = 0;
-    for (int k0 = kfirst; k0 <= klast; k0 += SS) {
-        const int R0 = k0 + 1;
-        const int nst = min(SS, klast - k0 + 1);
-        const int rlast = min(k0 + SS + 3, kb), clast = min(k0 + SS + 2, kb);
-        const int ccmin = (k0 == kfirst) ? 1 : 0; // column k0 lies outside the block at the introduction
-        // this thread's segment: a column right of the window (left products),
-        // a row above it, or a row of Z (right products)
-        const int ncL = max(0, colhi - clast), nrR = R0;
-        const int nseg = ncL + nrR + nz;
-        const int it = tid;
-        const bool seg = it < nseg;
-        const bool isL = it < ncL, isA = !isL && it - ncL < nrR;
-        double *base = (seg && !isL && !isA) ? Z : A;
-        const int ldb = (seg && !isL && !isA) ? ldz : lda;
-        // first entry and stride; nvalid entries exist (rows / columns <= kb)
-        const int prow = !seg ? 0 : (isL ? R0 : (isA ? it - ncL : it - ncL - nrR));
-        const int pcol = !seg ? 0 : (isL ? clast + 1 + it : R0);
-        const int st = (!seg || isL) ? 1 : ldb;
-        const int nvalid = !seg ? 0 : min(SS + 2, kb - R0 + 1);
-        double *p = base + prow + pcol * ldb;
-        double y[SS + 2];
-#pragma unroll
-        for (int j = 0; j < SS + 2; ++j) y[j] = (j < nvalid) ? p[j * st] : 0.0;
-        // the window
-        double W[WR][WR];
-#pragma unroll
-        for (int cc = 0; cc < WR; ++cc)
-#pragma unroll
-            for (int rr = 0; rr < WR; ++rr)
-                W[rr][cc] = (cc >= ccmin && k0 + cc <= clast && R0 + rr <= rlast)
-                                ? A[(R0 + rr) + (k0 + cc) * lda]
-                                : 0.0;
-        __syncthreads(); // every thread holds the window before anyone writes it back
-        double rv1[SS], rv2[SS], rtau[SS];
-        int rm[SS];
-#pragma unroll
-        for (int i = 0; i < SS; ++i) {
-            rtau[i] = 0.0;
-            rv1[i] = rv2[i] = 0.0;
-            rm[i] = 0;
-            if (i < nst) {
-                const int kl = k0 + i;
-                const int m = min(3, kb - kl);
-                double x0, x1, x2;
-                if (kl == kfirst) {
-                    // introduction (i = 0): first column of the shift polynomial
-                    const double h11 = W[0][1], h21 = W[1][1], h12 = W[0][2], h22 = W[1][2];
-                    const double h32 = (kt + 2 <= kb) ? W[2][2] : 0.0;
-                    const double sc = fabs(h11 - sr1) + fabs(si1) + fabs(h21);
-                    if (sc == 0.0) {
-                        x0 = x1 = x2 = 0.0;
-                    } else {
-                        const double f = h21 / sc;
-                        x0 = f * h12 + (h11 - sr0) * ((h11 - sr1) / sc) - si0 * (si1 / sc);
-                        x1 = f * (h11 + h22 - sr0 - sr1);
-                        x2 = f * h32;
-                    }
-                } else {
-                    x0 = W[i][i];
-                    x1 = W[i + 1][i];
-                    x2 = (m == 3) ? W[i + 2][i] : 0.0;
-                }
-                double v1, v2, tau, beta;
-                house3f(m, x0, x1, x2, v1, v2, tau, beta);
-                if (m < 3) v2 = 0.0;
-                rv1[i] = v1;
-                rv2[i] = v2;
-                rtau[i] = tau;
-                rm[i] = m;
-                if (tau != 0.0) {
-                    // left product on window rows i..i+m-1, columns right of the bulge column
-#pragma unroll
-                    for (int cc = i + 1; cc < WR; ++cc)
-                        refl3(m, tau, v1, v2, W[i][cc], W[i + 1][cc], W[i + 2][cc]);
-                    // right product on window columns i+1..i+m, rows 0..i+3
-#pragma unroll
-                    for (int rr = 0; rr <= i + 3; ++rr)
-                        refl3(m, tau, v1, v2, W[rr][i + 1], W[rr][i + 2], W[rr][i + 3]);
-                }
-                if (kl != kfirst) {
-                    W[i][i] = beta;
-                    W[i + 1][i] = 0.0;
-                    if (m == 3) W[i + 2][i] = 0.0;
-                }
-            }
-        }
-        // the thread's segment
-        if (seg) {
-#pragma unroll
-            for (int i = 0; i < SS; ++i)
-                if (rtau[i] != 0.0) refl3(rm[i], rtau[i], rv1[i], rv2[i], y[i], y[i + 1], y[i + 2]);
-#pragma unroll
-            for (int j = 0; j < SS + 2; ++j)
-                if (j < nvalid) p[j * st] = y[j];
-        }
-        // segments beyond the first NT (matrices with more rows than threads)
-        for (int it2 = tid + NT; it2 < nseg; it2 += NT) {
-            const bool L2 = it2 < ncL, A2 = !L2 && it2 - ncL < nrR;
-            double *q = (!L2 && !A2) ? Z : A;
-            const int ld2 = (!L2 && !A2) ? ldz : lda;
-            const int qr = L2 ? R0 : (A2 ? it2 - ncL : it2 - ncL - nrR);
-            const int qc = L2 ? clast + 1 + it2 : R0;
-            const int s2 = L2 ? 1 : ld2;
-            q += qr + qc * ld2;
-            double u[SS + 2];
-#pragma unroll
-            for (int j = 0; j < SS + 2; ++j) u[j] = (j < nvalid) ? q[j * s2] : 0.0;
-#pragma unroll
-            for (int i = 0; i < SS; ++i)
-                if (rtau[i] != 0.0) refl3(rm[i], rtau[i], rv1[i], rv2[i], u[i], u[i + 1], u[i + 2]);
-#pragma unroll
-            for (int j = 0; j < SS + 2; ++j)
-                if (j < nvalid) q[j * s2] = u[j];
-        }
-        // write the window back: lane 0 of wave w stores the entries f with
-        // f = w (mod 4); every thread holds the same window
-        if ((tid & 63) == 0) {
-            const int w = tid >> 6;
-#pragma unroll
-            for (int f = 0; f < WR * WR; ++f) {
-                const int rr = f % WR, cc = f / WR;
-                if ((f & 3) == w && cc >= ccmin && k0 + cc <= clast && R0 + rr <= rlast)
-                    A[(R0 + rr) + (k0 + cc) * lda] = W[rr][cc];
-            }
-        }
-        if (tid == 0) {
-            for (int i = 0; i < nst; ++i) {
-                const int kl = k0 + i, m = min(3, kb - kl);
-                const int extra = (m == 3 && kl + 4 <= kb) ? 1 : 0;
-                fl += 12.0 * (double)(max(0, colhi - kl - m) + kl + 1 + nz + extra) + 40.0;
-            }
-            nph += 1;
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        S.flops += fl;
-        S.nphase += nph;
-        S.nbstep += kb - kt;
-    }
-}
-
 // Largest l in (lo,hi] whose subdiagonal A[l,l-1] is zero or negligible
 // (then set to zero); lo if there is none.
 __device__ __forceinline__ int find_split(SmemCore &S, double *A, int lda, int lo, int hi, double smlnum)
@@ -947,7 +778,7 @@ __device__ __forceinline__ void ds_step(SmemCore &S, double *A, int lda, int m, 
         S.si[1] = i2;
     }
     __syncthreads();
-    chase_ws<4>(S, A, lda, l, i, m - 1, Z, ldz, nz);
+    chase1(S, A, lda, 0, l, i, l - 1, (i - 2) - (l - 1) + 1, i - 2, m - 1, Z, ldz, nz);
 }
 
 // Francis double-shift QR on the whole matrix A (order m, full T), Z accumulates.
@@ -1381,7 +1212,7 @@ __device__ bool swap_xform(double *Tw, int ldt, int j, double smlnum, double *Go
 // the deflated bottom counts as undeflated.  Returns the number of undeflated
 // leading rows.
 __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int sprow,
-                           double spscale, int ilst0, double smlnum)
+                           double spscale, int ilst0, double smlnum, int nforced = 0)
 {
     ReorderState &R = S.ro;
     const int tid = threadIdx.x;
@@ -1452,6 +1283,7 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
                                                 fabs(spscale * Z[sprow + (k - 1) * ldz]));
                         defl = spk <= fmax(smlnum, kU * hh);
                     }
+                    if (cand >= nt - nforced) defl = false; // failed in an earlier deflation window
                     if (defl) {
                         ns -= csz;
                         continue;
@@ -1970,7 +1802,7 @@ __global__ void __launch_bounds__(NT) k_chase(double *H, int64_t ld, ChaseRound 
 // Corner deflation of a large AED window held in global memory.
 __global__ void __launch_bounds__(NT) k_corner_deflate(double *T, int64_t ldt, int nw, int wd, const double *V,
                                                        int64_t ldv, double s, double smlnum, double *Ut,
-                                                       IterStatus *st)
+                                                       IterStatus *st, int nforced)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem &S = *reinterpret_cast<Smem *>(smem_raw);
@@ -1988,7 +1820,8 @@ __global__ void __launch_bounds__(NT) k_corner_deflate(double *T, int64_t ldt, i
     for (int c = tid; c < wd; c += NT) S.Z[wd + c * LDM] = s * V[(int64_t)(c0 + c) * ldv];
     if (tid == 0) S.nswap = S.nrphase = 0;
     __syncthreads();
-    int nsc = aed_deflate(S, S.A, LDM, wd, S.Z, LDM, wd + 1, wd, 1.0, 0, smlnum);
+    int nsc = aed_deflate(S, S.A, LDM, wd, S.Z, LDM, wd + 1, wd, 1.0, 0, smlnum, min(nforced, wd));
+    const int halted = S.ro.halt;
     __syncthreads();
     for (int it = tid; it < wd * wd; it += NT) {
         int r = it % wd, c = it / wd;
@@ -2000,6 +1833,7 @@ __global__ void __launch_bounds__(NT) k_corner_deflate(double *T, int64_t ldt, i
         st->nd = nw - (c0 + nsc);
         st->kwtop = c0; // corner offset
         st->nw = wd;
+        st->info = halted;
     }
 }
 
@@ -2292,12 +2126,13 @@ hipError_t launch_chase(double *H, int64_t ld, const ChaseRound &r, const double
 }
 
 hipError_t launch_corner_deflate(double *T, int64_t ldt, int nw, int wd, const double *V, int64_t ldv,
-                                 double s, double smlnum, double *Ut, IterStatus *st, hipStream_t stream)
+                                 double s, double smlnum, double *Ut, IterStatus *st, int nforced,
+                                 hipStream_t stream)
 {
     hipError_t e = prep((const void *)k_corner_deflate);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_corner_deflate, dim3(1), dim3(NT), smem_bytes(), stream, T, ldt, nw, wd, V, ldv, s,
-                       smlnum, Ut, st);
+                       smlnum, Ut, st, nforced);
     return hipGetLastError();
 }
 
