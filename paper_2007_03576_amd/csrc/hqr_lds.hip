@@ -496,16 +496,51 @@ __device__ __forceinline__ void chain_chase(SmemCore &S, double *A, int lda, int
     if (tid == 0) S.flops += fl;
 }
 
+// 1/d from the hardware reciprocal and one Newton step (a few ulps).
+__device__ inline double rcp_nr(double d)
+{
+    const double r = __builtin_amdgcn_rcp(d);
+    return fma(r, fma(-d, r, 1.0), r);
+}
+
+// house3f for the chase: the two quotients from reciprocals.  The reflector
+// stays orthogonal to working accuracy (tau and v carry errors of a few ulps).
+__device__ inline void house3c(int m, double x0, double x1, double x2, double &v1, double &v2, double &tau,
+                               double &beta)
+{
+    const double t1 = (m > 1) ? x1 : 0.0, t2 = (m > 2) ? x2 : 0.0;
+    if (t1 == 0.0 && t2 == 0.0) {
+        tau = 0.0;
+        beta = x0;
+        v1 = v2 = 0.0;
+        return;
+    }
+    const double amax = fmax(fabs(x0), fmax(fabs(t1), fabs(t2)));
+    if (!(amax > 0x1p-450 && amax < 0x1p+450)) {
+        house3(m, x0, x1, x2, v1, v2, tau, beta);
+        return;
+    }
+    const double nrm = sqrt(fma(x0, x0, fma(t1, t1, t2 * t2)));
+    const double b = (x0 >= 0.0) ? -nrm : nrm;
+    const double d = x0 - b; // |d| = |x0| + nrm
+    const double rd = rcp_nr(d);
+    tau = -d * rcp_nr(b);
+    v1 = t1 * rd;
+    v2 = t2 * rd;
+    beta = b;
+}
+
 // Single-bulge chase (one double-shift sweep) through the matrix held in LDS:
 // the reflector at k acts on rows/columns k+1..k+m of the active block
 // [ktop,kbot] (indices global, local = global - off), left products on local
 // columns up to colhi, right products on local rows 0..k+4 and on the nz rows
 // of Z.  One barrier per step.  Every thread computes the reflector itself;
 // the entries a thread updates are loaded before the reflector is formed, so
-// their latency hides behind it.  The item of one thread is a column segment
-// (left product), a row segment (right product) or, for one thread, the 3x3
-// block on the diagonal (both products); the new bulge column is written one
-// step later, when nobody reads it.
+// their latency hides behind it.  Items: the nine entries of the diagonal
+// block B (both products, B <- P B P entry by entry from u = B v, w = B^T v
+// and v^T B v, threads 0..8), then row and column segments of three entries
+// (one product each) on the other threads and round-robin beyond; the new
+// bulge column is written one step later, when nobody reads it.
 __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off, int ktop, int kbot, int p0,
                                        int nsteps, int kend, int colhi, double *Z, int ldz, int nz)
 {
@@ -514,6 +549,7 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
     int pend_kl = -1, pend_m = 0, nph = 0;
     double pend_beta = 0.0;
     double fl = 0.0;
+    const int er = tid % 3, ec = tid / 3; // this thread's entry of the diagonal block (tid < 9)
     for (int t = 0; t < nsteps; ++t) {
         const int k = p0 + t;
         if (k < ktop - 1 || k > kend) continue;
@@ -525,28 +561,24 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
         const int nrR = kl + 1;
         const bool extra = (m == 3 && kl + 4 <= kbl);
         const int perR = nrR + nz + (extra ? 1 : 0);
-        const int own = ncL + perR;  // number of row/column segments
-        const int total = own + 1;     // and the diagonal block
-        // the diagonal block goes to thread ownidx, the segments to the other
-        // threads in order, then round-robin over all threads
-        const int ownidx = min(own, NT - 1);
-        const bool mine = (tid == ownidx);
-        const int it = (tid < ownidx) ? tid : tid - 1;
-        const bool seg = !mine && it < own;
+        const int nseg = ncL + perR; // row/column segments, items 9.. (items 0..8: the diagonal block)
+        const bool mine = tid < 9 && er < m && ec < m;
+        const int it = tid - 9;
+        const bool seg = tid >= 9 && it < nseg;
         double sx0 = 0.0, sx1 = 0.0, sx2 = 0.0;
         if (intro) {
             shift_column(A, lda, kl + 1, kbl, S.sr[0], S.si[0], S.sr[1], S.si[1], sx0, sx1, sx2);
             __syncthreads(); // the leading block is read before anyone overwrites it
         }
-        // Loads in the order the data is needed: the diagonal block (one
-        // thread), the bulge column, then this thread's segment.  The column
+        // Loads in the order the data is needed: the diagonal block (threads
+        // 0..8), the bulge column, then this thread's segment.  The column
         // and segment loads are unconditional (a harmless in-bounds address
         // where there is nothing to load) so that waiting for the column does
         // not wait for the segment, whose latency then hides behind the
         // reflector.
         double B00 = 0.0, B01 = 0.0, B02 = 0.0, B10 = 0.0, B11 = 0.0, B12 = 0.0, B20 = 0.0, B21 = 0.0, B22 = 0.0;
         double *a = A + (kl + 1) + (kl + 1) * lda;
-        if (mine) {
+        if (tid < 9) {
             B00 = a[0];
             B10 = a[1];
             B01 = a[lda];
@@ -581,8 +613,10 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
             x2 = 0.0;
             y2 = 0.0;
         }
+        // threads 0..8 (one wave) all read B before any of them writes its entry
+        __builtin_amdgcn_wave_barrier();
         double v1, v2, tau, beta;
-        house3f(m, x0, x1, x2, v1, v2, tau, beta);
+        house3c(m, x0, x1, x2, v1, v2, tau, beta);
         if (m < 3) v2 = 0.0;
         if (tau != 0.0) {
             if (seg) {
@@ -591,38 +625,35 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
                 p[st] = y1;
                 if (m == 3) p[2 * st] = y2;
             } else if (mine) {
-                refl3(3, tau, v1, v2, B00, B10, B20);
-                refl3(3, tau, v1, v2, B01, B11, B21);
-                refl3(3, tau, v1, v2, B02, B12, B22);
-                refl3(3, tau, v1, v2, B00, B01, B02);
-                refl3(3, tau, v1, v2, B10, B11, B12);
-                refl3(3, tau, v1, v2, B20, B21, B22);
-                a[0] = B00;
-                a[1] = B10;
-                a[lda] = B01;
-                a[1 + lda] = B11;
-                if (m == 3) {
-                    a[2] = B20;
-                    a[2 + lda] = B21;
-                    a[2 * lda] = B02;
-                    a[1 + 2 * lda] = B12;
-                    a[2 + 2 * lda] = B22;
-                }
+                // B' = B - tau v w^T - tau u v^T + tau^2 (v^T u) v v^T
+                const double u0 = B00 + v1 * B01 + v2 * B02;
+                const double u1 = B10 + v1 * B11 + v2 * B12;
+                const double u2 = B20 + v1 * B21 + v2 * B22;
+                const double gam = u0 + v1 * u1 + v2 * u2;
+                const double vr = (er == 0) ? 1.0 : (er == 1 ? v1 : v2);
+                const double vc = (ec == 0) ? 1.0 : (ec == 1 ? v1 : v2);
+                const double ur = (er == 0) ? u0 : (er == 1 ? u1 : u2);
+                const double b0c = (ec == 0) ? B00 : (ec == 1 ? B01 : B02);
+                const double b1c = (ec == 0) ? B10 : (ec == 1 ? B11 : B12);
+                const double b2c = (ec == 0) ? B20 : (ec == 1 ? B21 : B22);
+                const double wc = b0c + v1 * b1c + v2 * b2c;
+                const double brc = (er == 0) ? b0c : (er == 1 ? b1c : b2c);
+                a[er + ec * lda] = brc - tau * (vr * wc + ur * vc) + tau * tau * gam * vr * vc;
             }
-            // further items (matrices with more rows than threads)
-            for (int it2 = tid + NT - 1; it2 < own; it2 += NT) {
+            // further segments (matrices with more rows than threads)
+            for (int it2 = tid + NT - 9; it2 < nseg; it2 += NT) {
                 double *q;
                 int sq;
                 if (it2 < ncL) {
                     q = A + (c0L + it2) * lda + (kl + 1);
                     sq = 1;
                 } else {
-                    const int r = it2 - ncL;
-                    if (r < nrR) {
-                        q = A + r + (kl + 1) * lda;
+                    const int r2 = it2 - ncL;
+                    if (r2 < nrR) {
+                        q = A + r2 + (kl + 1) * lda;
                         sq = lda;
-                    } else if (r < nrR + nz) {
-                        q = Z + (r - nrR) + (kl + 1) * ldz;
+                    } else if (r2 < nrR + nz) {
+                        q = Z + (r2 - nrR) + (kl + 1) * ldz;
                         sq = ldz;
                     } else {
                         q = A + (kl + 4) + (kl + 1) * lda;
@@ -645,7 +676,7 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
             pend_m = intro ? 0 : m;
             pend_kl = kl;
             pend_beta = beta;
-            fl += 4.0 * 3.0 * (double)(total - 1) + 40.0;
+            fl += 4.0 * 3.0 * (double)nseg + 40.0;
             ++nph;
         }
         __syncthreads();
