@@ -496,15 +496,17 @@ __device__ __forceinline__ void chain_chase(SmemCore &S, double *A, int lda, int
     if (tid == 0) S.flops += fl;
 }
 
-// 1/d from the hardware reciprocal and one Newton step (a few ulps).
+// 1/d from the hardware reciprocal (about 28 correct bits) and two Newton
+// steps (within an ulp; measured 0.5 ulp over binades 2^-100..2^100).
 __device__ inline double rcp_nr(double d)
 {
-    const double r = __builtin_amdgcn_rcp(d);
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
     return fma(r, fma(-d, r, 1.0), r);
 }
 
-// house3f for the chase: the two quotients from reciprocals.  The reflector
-// stays orthogonal to working accuracy (tau and v carry errors of a few ulps).
+// house3f for the chase: the two quotients from reciprocals (shorter
+// dependency chains than correctly rounded division, same accuracy class).
 __device__ inline void house3c(int m, double x0, double x1, double x2, double &v1, double &v2, double &tau,
                                double &beta)
 {
@@ -536,11 +538,13 @@ __device__ inline void house3c(int m, double x0, double x1, double x2, double &v
 // columns up to colhi, right products on local rows 0..k+4 and on the nz rows
 // of Z.  One barrier per step.  Every thread computes the reflector itself;
 // the entries a thread updates are loaded before the reflector is formed, so
-// their latency hides behind it.  Items: the nine entries of the diagonal
-// block B (both products, B <- P B P entry by entry from u = B v, w = B^T v
-// and v^T B v, threads 0..8), then row and column segments of three entries
-// (one product each) on the other threads and round-robin beyond; the new
-// bulge column is written one step later, when nobody reads it.
+// their latency hides behind it.  Items: row and column segments of three
+// entries (one product each) on threads 0..NT-11 and round-robin beyond; the
+// nine entries of the diagonal block B (both products, B <- P B P entry by
+// entry from u = B v, w = B^T v and v^T B v) on the last nine threads, and
+// the bulge column on thread NT-10, written one step later when nobody reads
+// it.  The last wave has no segments while the block has at most 246 of
+// them, so its longer chains do not hold up the others.
 __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off, int ktop, int kbot, int p0,
                                        int nsteps, int kend, int colhi, double *Z, int ldz, int nz)
 {
@@ -549,7 +553,8 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
     int pend_kl = -1, pend_m = 0, nph = 0;
     double pend_beta = 0.0;
     double fl = 0.0;
-    const int er = tid % 3, ec = tid / 3; // this thread's entry of the diagonal block (tid < 9)
+    constexpr int OWN0 = NT - 9, PEND = NT - 10, NSEG1 = NT - 10;
+    const int er = (tid - OWN0) % 3, ec = (tid - OWN0) / 3; // entry of the diagonal block (tid >= OWN0)
     for (int t = 0; t < nsteps; ++t) {
         const int k = p0 + t;
         if (k < ktop - 1 || k > kend) continue;
@@ -561,24 +566,25 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
         const int nrR = kl + 1;
         const bool extra = (m == 3 && kl + 4 <= kbl);
         const int perR = nrR + nz + (extra ? 1 : 0);
-        const int nseg = ncL + perR; // row/column segments, items 9.. (items 0..8: the diagonal block)
-        const bool mine = tid < 9 && er < m && ec < m;
-        const int it = tid - 9;
-        const bool seg = tid >= 9 && it < nseg;
+        const int nseg = ncL + perR; // row/column segments
+        const bool own = tid >= OWN0;
+        const bool mine = own && er < m && ec < m;
+        const int it = tid;
+        const bool seg = tid < NSEG1 && it < nseg;
         double sx0 = 0.0, sx1 = 0.0, sx2 = 0.0;
         if (intro) {
             shift_column(A, lda, kl + 1, kbl, S.sr[0], S.si[0], S.sr[1], S.si[1], sx0, sx1, sx2);
             __syncthreads(); // the leading block is read before anyone overwrites it
         }
-        // Loads in the order the data is needed: the diagonal block (threads
-        // 0..8), the bulge column, then this thread's segment.  The column
+        // Loads in the order the data is needed: the diagonal block (last
+        // nine threads), the bulge column, then this thread's segment.  The column
         // and segment loads are unconditional (a harmless in-bounds address
         // where there is nothing to load) so that waiting for the column does
         // not wait for the segment, whose latency then hides behind the
         // reflector.
         double B00 = 0.0, B01 = 0.0, B02 = 0.0, B10 = 0.0, B11 = 0.0, B12 = 0.0, B20 = 0.0, B21 = 0.0, B22 = 0.0;
         double *a = A + (kl + 1) + (kl + 1) * lda;
-        if (tid < 9) {
+        if (own) {
             B00 = a[0];
             B10 = a[1];
             B01 = a[lda];
@@ -613,7 +619,7 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
             x2 = 0.0;
             y2 = 0.0;
         }
-        // threads 0..8 (one wave) all read B before any of them writes its entry
+        // the last nine threads (one wave) all read B before any of them writes its entry
         __builtin_amdgcn_wave_barrier();
         double v1, v2, tau, beta;
         house3c(m, x0, x1, x2, v1, v2, tau, beta);
@@ -641,7 +647,7 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
                 a[er + ec * lda] = brc - tau * (vr * wc + ur * vc) + tau * tau * gam * vr * vc;
             }
             // further segments (matrices with more rows than threads)
-            for (int it2 = tid + NT - 9; it2 < nseg; it2 += NT) {
+            for (int it2 = tid + NSEG1; it2 < nseg; it2 += NT) {
                 double *q;
                 int sq;
                 if (it2 < ncL) {
@@ -667,7 +673,7 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
                 if (m == 3) q[2 * sq] = z2;
             }
         }
-        if (tid == 0) {
+        if (tid == PEND) {
             if (pend_m > 0) {
                 A[(pend_kl + 1) + pend_kl * lda] = pend_beta;
                 A[(pend_kl + 2) + pend_kl * lda] = 0.0;
@@ -681,7 +687,7 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
         }
         __syncthreads();
     }
-    if (tid == 0) {
+    if (tid == PEND) {
         if (pend_m > 0) {
             A[(pend_kl + 1) + pend_kl * lda] = pend_beta;
             A[(pend_kl + 2) + pend_kl * lda] = 0.0;
