@@ -35,6 +35,30 @@ def make_input(spec, seed):
     return H
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated with a plain copy), or None when the
+    HIP sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_iter_gaussian_hessenberg_n4096.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("pmc-json:"):
+            rec = json.loads(line.split(":", 1)[1])
+    if rec is None or rec.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2007_03576_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h")):
+            h.update(open(f, "rb").read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def cpu_baseline(spec, seed, target_n):
     """The oracle on a bounded sample of the same workload (same generator
     and parameters, order target_n), single thread; returns nominal TFLOP/s."""
@@ -152,6 +176,8 @@ def main():
         "run_stats": stats,
     }
     out["roofline"] = profiling.roofline(prof, args.steps)
+    if args.workload == "gaussian_hessenberg_n4096":
+        out["roofline"]["traffic"] = measured_traffic(out["roofline"]["kernel"])
     out["kernel_times"] = profiling.summary(prof, args.steps)
     out["kernel_times"]["lds_iteration"]["split"] = lds_split
     if not args.no_cpu_baseline:
