@@ -700,6 +700,155 @@ __device__ __forceinline__ void chase1(SmemCore &S, double *A, int lda, int off,
     __syncthreads();
 }
 
+// Broadcast of a double held by one lane of the wave (scalar read of the lane).
+__device__ inline double lane_bcast(double v, int src)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+// Single-bulge sweep (one double-shift step) over the active block [kt,kb]
+// of the matrix in LDS (local indices), left products on columns up to colhi,
+// right products on rows 0..k+4 and on the nz rows of Z, with a one-step
+// lookahead on the reflectors.  The last wave (the core) owns the 3x3
+// diagonal block B (rows/columns k+1..k+3): at position k its lanes 0..8 load
+// B and form one entry each of P B P (from u = B v, w = B^T v and v^T B v),
+// lanes 9..11 write the bulge column (beta, 0, 0); the two entries of P B P in
+// the next bulge column reach every lane by a scalar lane read, and with the
+// fill-in of row k+4 (-tau v2 h, h the untouched subdiagonal entry below the
+// block) the core forms the reflector of position k+1 and passes it on
+// through LDS.  The other waves read the reflector of position k from LDS and
+// apply it to the row and column segments of three entries outside the
+// block.  Nothing the core reads at position k is written by another wave at
+// position k, so one barrier per position suffices, and the reflector is
+// formed once per position, off the segment waves' path.
+__device__ __forceinline__ void chase_la(SmemCore &S, double *A, int lda, int kt, int kb, int colhi, double *Z,
+                                         int ldz, int nz)
+{
+    constexpr int NSEGT = NT - 64; // threads of the segment waves
+    const int tid = threadIdx.x;
+    const bool core = tid >= NSEGT;
+    const int lane = tid - NSEGT;
+    const int er = lane % 3, ec = lane / 3; // this lane's entry of the block (lanes 0..8)
+    const int kfirst = kt - 1, klast = kb - 2;
+    double fl = 0.0;
+    double cv1 = 0.0, cv2 = 0.0, ctau = 0.0, cbeta = 0.0, ch = 0.0;
+    if (core) {
+        const double *a = A + kt + kt * lda;
+        const double h11 = a[0], h21 = a[1], h12 = a[lda], h22 = a[1 + lda];
+        const double h32 = (kt + 2 <= kb) ? a[2 + lda] : 0.0;
+        ch = (kt + 3 <= kb) ? A[(kt + 3) + (kt + 2) * lda] : 0.0;
+        const double sr0 = S.sr[0], si0 = S.si[0], sr1 = S.sr[1], si1 = S.si[1];
+        const double sc = fabs(h11 - sr1) + fabs(si1) + fabs(h21);
+        double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+        if (sc != 0.0) {
+            const double f = h21 / sc;
+            x0 = f * h12 + (h11 - sr0) * ((h11 - sr1) / sc) - si0 * (si1 / sc);
+            x1 = f * (h11 + h22 - sr0 - sr1);
+            x2 = f * h32;
+        }
+        const int m0 = min(3, kb - kfirst);
+        house3c(m0, x0, x1, x2, cv1, cv2, ctau, cbeta);
+        if (m0 < 3) cv2 = 0.0;
+        if (lane == 0) {
+            S.bv1[0] = cv1;
+            S.bv2[0] = cv2;
+            S.btau[0] = ctau;
+        }
+    }
+    __syncthreads();
+    for (int k = kfirst; k <= klast; ++k) {
+        const int par = (k - kfirst) & 1;
+        const int m = min(3, kb - k);
+        const bool extra = (m == 3 && k + 4 <= kb);
+        if (!core) {
+            const double v1 = S.bv1[par], v2 = S.bv2[par], tau = S.btau[par];
+            const int c0L = k + m + 1;
+            const int ncL = max(0, colhi - c0L + 1), nrR = k + 1;
+            const int nseg = ncL + nrR + nz + (extra ? 1 : 0);
+            for (int it = tid; it < nseg; it += NSEGT) {
+                const int r = it - ncL;
+                const bool isL = it < ncL, isA = !isL && r < nrR, isZ = !isL && !isA && r < nrR + nz;
+                double *base = isZ ? Z : A;
+                const int ldb = isZ ? ldz : lda;
+                const int prow = isL ? (k + 1) : (isA ? r : (isZ ? r - nrR : k + 4));
+                const int pcol = isL ? (c0L + it) : (k + 1);
+                const int st = isL ? 1 : ldb;
+                double *p = base + prow + pcol * ldb;
+                double y0 = p[0], y1 = p[st], y2 = (m == 3) ? p[2 * st] : 0.0;
+                if (tau != 0.0) {
+                    refl3(m, tau, v1, v2, y0, y1, y2);
+                    p[0] = y0;
+                    p[st] = y1;
+                    if (m == 3) p[2 * st] = y2;
+                }
+            }
+            if (tid == 0) fl += 12.0 * (double)nseg + 40.0;
+        } else {
+            // the block, final since the last barrier and written below only by the core
+            const double *a = A + (k + 1) + (k + 1) * lda;
+            const double B00 = a[0], B10 = a[1], B01 = a[lda], B11 = a[1 + lda];
+            const double B20 = (m == 3) ? a[2] : 0.0, B21 = (m == 3) ? a[2 + lda] : 0.0;
+            const double B02 = (m == 3) ? a[2 * lda] : 0.0, B12 = (m == 3) ? a[1 + 2 * lda] : 0.0;
+            const double B22 = (m == 3) ? a[2 + 2 * lda] : 0.0;
+            const double hn = (k + 5 <= kb) ? A[(k + 5) + (k + 4) * lda] : 0.0;
+            __builtin_amdgcn_wave_barrier(); // every core lane has read B before any writes it
+            // this lane's entry of P B P = B - tau v w^T - tau u v^T + tau^2 (v^T u) v v^T
+            const double v1 = cv1, v2 = cv2, tau = ctau;
+            const double b0c = (ec == 0) ? B00 : (ec == 1 ? B01 : B02);
+            const double b1c = (ec == 0) ? B10 : (ec == 1 ? B11 : B12);
+            const double b2c = (ec == 0) ? B20 : (ec == 1 ? B21 : B22);
+            double val = (er == 0) ? b0c : (er == 1 ? b1c : b2c);
+            if (tau != 0.0) {
+                const double u0 = B00 + v1 * B01 + v2 * B02;
+                const double u1 = B10 + v1 * B11 + v2 * B12;
+                const double u2 = B20 + v1 * B21 + v2 * B22;
+                const double gam = u0 + v1 * u1 + v2 * u2;
+                const double wc = b0c + v1 * b1c + v2 * b2c;
+                const double vr = (er == 0) ? 1.0 : (er == 1 ? v1 : v2);
+                const double vc = (ec == 0) ? 1.0 : (ec == 1 ? v1 : v2);
+                const double ur = (er == 0) ? u0 : (er == 1 ? u1 : u2);
+                val = val - tau * (vr * wc + ur * vc) + tau * tau * gam * vr * vc;
+            }
+            if (k < klast) {
+                // reflector of position k+1 from rows k+2..k+4 of column k+1:
+                // entries (1,0) and (2,0) of P B P (lanes 1 and 2) and the fill-in of row k+4
+                const double x0 = lane_bcast(val, 1), x1 = lane_bcast(val, 2);
+                const int m1 = min(3, kb - (k + 1));
+                const double r0 = (extra && tau != 0.0) ? -(tau * (v2 * ch)) : 0.0; // as the row segment computes it
+                double nv1, nv2, ntau, nbeta;
+                house3c(m1, x0, x1, (m1 == 3) ? r0 : 0.0, nv1, nv2, ntau, nbeta);
+                if (m1 < 3) nv2 = 0.0;
+                if (lane == 0) {
+                    S.bv1[par ^ 1] = nv1;
+                    S.bv2[par ^ 1] = nv2;
+                    S.btau[par ^ 1] = ntau;
+                }
+                if (lane < 9 && er < m && ec < m) A[(k + 1 + er) + (k + 1 + ec) * lda] = val;
+                if (lane >= 9 && lane < 12 && k > kfirst && lane - 9 < m)
+                    A[(k + lane - 8) + k * lda] = (lane == 9) ? cbeta : 0.0;
+                cv1 = nv1;
+                cv2 = nv2;
+                ctau = ntau;
+                cbeta = nbeta;
+                ch = hn;
+            } else {
+                if (lane < 9 && er < m && ec < m) A[(k + 1 + er) + (k + 1 + ec) * lda] = val;
+                if (lane >= 9 && lane < 12 && k > kfirst && lane - 9 < m)
+                    A[(k + lane - 8) + k * lda] = (lane == 9) ? cbeta : 0.0;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        S.flops += fl;
+        S.nphase += klast - kfirst + 1;
+        S.nbstep += klast - kfirst + 1;
+    }
+    __syncthreads();
+}
+
 // Largest l in (lo,hi] whose subdiagonal A[l,l-1] is zero or negligible
 // (then set to zero); lo if there is none.
 __device__ __forceinline__ int find_split(SmemCore &S, double *A, int lda, int lo, int hi, double smlnum)
@@ -815,7 +964,7 @@ __device__ __forceinline__ void ds_step(SmemCore &S, double *A, int lda, int m, 
         S.si[1] = i2;
     }
     __syncthreads();
-    chase1(S, A, lda, 0, l, i, l - 1, (i - 2) - (l - 1) + 1, i - 2, m - 1, Z, ldz, nz);
+    chase_la(S, A, lda, l, i, m - 1, Z, ldz, nz);
 }
 
 // Francis double-shift QR on the whole matrix A (order m, full T), Z accumulates.
