@@ -511,18 +511,11 @@ __device__ inline void house3c(int m, double x0, double x1, double x2, double &v
                                double &beta)
 {
     const double t1 = (m > 1) ? x1 : 0.0, t2 = (m > 2) ? x2 : 0.0;
-    if (t1 == 0.0 && t2 == 0.0) {
-        tau = 0.0;
-        beta = x0;
-        v1 = v2 = 0.0;
-        return;
-    }
-    const double amax = fmax(fabs(x0), fmax(fabs(t1), fabs(t2)));
-    if (!(amax > 0x1p-450 && amax < 0x1p+450)) {
-        house3(m, x0, x1, x2, v1, v2, tau, beta);
-        return;
-    }
-    const double nrm = sqrt(fma(x0, x0, fma(t1, t1, t2 * t2)));
+    // fast path: squares neither overflow nor underflow (checked alongside,
+    // on ss, and redone with the scaled form when they might)
+    const double q = fma(t1, t1, t2 * t2);
+    const double ss = fma(x0, x0, q);
+    const double nrm = sqrt(ss);
     const double b = (x0 >= 0.0) ? -nrm : nrm;
     const double d = x0 - b; // |d| = |x0| + nrm
     const double rd = rcp_nr(d);
@@ -530,6 +523,15 @@ __device__ inline void house3c(int m, double x0, double x1, double x2, double &v
     v1 = t1 * rd;
     v2 = t2 * rd;
     beta = b;
+    if (!(ss > 0x1p-900 && ss < 0x1p+900 && q > 0x1p-900)) {
+        if (t1 == 0.0 && t2 == 0.0) {
+            tau = 0.0;
+            beta = x0;
+            v1 = v2 = 0.0;
+        } else {
+            house3(m, x0, x1, x2, v1, v2, tau, beta);
+        }
+    }
 }
 
 // Single-bulge chase (one double-shift sweep) through the matrix held in LDS:
@@ -811,6 +813,10 @@ __device__ __forceinline__ void chase_la(SmemCore &S, double *A, int lda, int kt
                 const double ur = (er == 0) ? u0 : (er == 1 ? u1 : u2);
                 val = val - tau * (vr * wc + ur * vc) + tau * tau * gam * vr * vc;
             }
+            // the block and the bulge column first: their stores overlap the reflector below
+            if (lane < 9 && er < m && ec < m) A[(k + 1 + er) + (k + 1 + ec) * lda] = val;
+            if (lane >= 9 && lane < 12 && k > kfirst && lane - 9 < m)
+                A[(k + lane - 8) + k * lda] = (lane == 9) ? cbeta : 0.0;
             if (k < klast) {
                 // reflector of position k+1 from rows k+2..k+4 of column k+1:
                 // entries (1,0) and (2,0) of P B P (lanes 1 and 2) and the fill-in of row k+4
@@ -825,18 +831,11 @@ __device__ __forceinline__ void chase_la(SmemCore &S, double *A, int lda, int kt
                     S.bv2[par ^ 1] = nv2;
                     S.btau[par ^ 1] = ntau;
                 }
-                if (lane < 9 && er < m && ec < m) A[(k + 1 + er) + (k + 1 + ec) * lda] = val;
-                if (lane >= 9 && lane < 12 && k > kfirst && lane - 9 < m)
-                    A[(k + lane - 8) + k * lda] = (lane == 9) ? cbeta : 0.0;
                 cv1 = nv1;
                 cv2 = nv2;
                 ctau = ntau;
                 cbeta = nbeta;
                 ch = hn;
-            } else {
-                if (lane < 9 && er < m && ec < m) A[(k + 1 + er) + (k + 1 + ec) * lda] = val;
-                if (lane >= 9 && lane < 12 && k > kfirst && lane - 9 < m)
-                    A[(k + lane - 8) + k * lda] = (lane == 9) ? cbeta : 0.0;
             }
         }
         __syncthreads();
