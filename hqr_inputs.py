@@ -246,6 +246,63 @@ def hessenberg_reduce_torch(A):
     return torch.triu(A, -1)
 
 
+def hessenberg_reduce_torch_batched(A):
+    """Unblocked Householder reduction of a stack of square matrices (B, n, n)
+    to upper Hessenberg form, vectorized over the stack (input preparation of
+    the differentiation benchmark).  Returns the Hessenberg matrices with
+    exact zeros below the subdiagonal; the orthogonal factors are not formed."""
+    import torch
+    A = A.clone()
+    B, n, _ = A.shape
+    for k in range(n - 2):
+        x = A[:, k + 1:, k]                                   # (B, n-k-1)
+        alpha = x[:, 0]
+        tail = torch.linalg.vector_norm(x[:, 1:], dim=1)
+        nrm = torch.hypot(alpha, tail)
+        beta = torch.where(alpha >= 0, -nrm, nrm)
+        live = tail > 0
+        denom = torch.where(live, alpha - beta, torch.ones_like(alpha))
+        tau = torch.where(live, (beta - alpha) / torch.where(live, beta, torch.ones_like(beta)),
+                          torch.zeros_like(beta))
+        v = x / denom[:, None]
+        v[:, 0] = 1.0
+        # left: rows k+1.., columns k..
+        sub = A[:, k + 1:, k:]
+        w = torch.einsum("bi,bij->bj", v, sub)
+        sub -= tau[:, None, None] * v[:, :, None] * w[:, None, :]
+        # right: all rows, columns k+1..
+        right = A[:, :, k + 1:]
+        z = torch.einsum("bij,bj->bi", right, v)
+        right -= tau[:, None, None] * z[:, :, None] * v[:, None, :]
+        A[:, k + 2:, k] = 0.0
+        A[:, k + 1, k] = torch.where(live, beta, alpha)
+    return torch.triu(A, -1)
+
+
+def prescribed_batch_device(count: int, n: int, seed: int = SEED, device="cuda"):
+    """Stack of `count` Hessenberg matrices of order n with well-separated
+    prescribed spectra (n/2 reals on a jittered grid, n/4 pairs drawn by
+    rejection; every two eigenvalues at least 0.05 apart), each a Haar
+    orthogonal similarity of its block diagonal, reduced on the GPU.
+    Returns (H (count, n, n) row-major device tensor, eigenvalues list)."""
+    import torch
+    g = rng(seed)
+    n_pairs = n // 4
+    n_real = n - 2 * n_pairs
+    Ls, eigs = [], []
+    for _ in range(count):
+        reals, a, b = separated_spectrum(n_real, n_pairs, g)
+        Ls.append(blockdiag_from_spectrum(reals, a, b))
+        eigs.append(eigs_from_spectrum(reals, a, b))
+    L = torch.from_numpy(np.stack(Ls)).to(device)
+    Z = torch.from_numpy(g.standard_normal((count, n, n))).to(device)
+    W, R = torch.linalg.qr(Z)
+    d = torch.diagonal(R, dim1=1, dim2=2)
+    W = W * torch.where(d < 0, -torch.ones_like(d), torch.ones_like(d))[:, None, :]
+    A = torch.bmm(torch.bmm(W, L), W.transpose(1, 2).contiguous())
+    return hessenberg_reduce_torch_batched(A), eigs
+
+
 def prescribed_hessenberg_device(n: int, seed: int = SEED, device="cuda"):
     """prescribed_hessenberg built on the GPU with torch (Haar W by QR, A = W L W^T,
     Householder Hessenberg reduction).  Returns (H row-major device tensor, eigenvalues)."""

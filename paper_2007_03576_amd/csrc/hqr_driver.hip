@@ -17,6 +17,8 @@
 #include "hqr_common.h"
 #include "../../include/hqr.h"
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <cfloat>
 #include <cmath>
 #include <cstdlib>
@@ -538,6 +540,25 @@ int sweep(Ctx &C, const View &V, int ktop, int kbot, int nsh, const double *sr, 
 
 int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int *info_out);
 
+// Optional progress report of long solves (environment HQR_PROGRESS=1): one
+// line on stderr per top-level AED step, at most one every two seconds.
+void progress_line(int ilo, int kbot, int nd)
+{
+    static int enabled = -1;
+    static std::chrono::steady_clock::time_point last;
+    if (enabled < 0) {
+        const char *e = std::getenv("HQR_PROGRESS");
+        enabled = (e && e[0] == '1') ? 1 : 0;
+        last = std::chrono::steady_clock::now() - std::chrono::seconds(10);
+    }
+    if (!enabled) return;
+    const auto now = std::chrono::steady_clock::now();
+    if (now - last < std::chrono::seconds(2)) return;
+    last = now;
+    std::fprintf(stderr, "hqr: AED step deflated %d, %d rows left above row %d\n", nd, kbot - ilo + 1, ilo);
+    std::fflush(stderr);
+}
+
 // AED step with a window larger than the LDS solver: recursive Schur form of
 // a copy of the window, corner deflation, Hessenberg restoration.
 int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd, int &ns, int &ncand)
@@ -755,6 +776,7 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
             C.stats[0]++;
             C.stats[3] += nd;
         }
+        if (depth == 0) progress_line(ilo, kbot - nd, nd);
         cr.assign(S.cr, S.cr + ncand);
         ci.assign(S.ci, S.ci + ncand);
         kbot -= nd;
