@@ -246,6 +246,67 @@ def hessenberg_reduce_torch(A):
     return torch.triu(A, -1)
 
 
+def hessenberg_reduce_blocked(A, nb: int = 64, progress=None):
+    """Blocked Householder reduction of a square device matrix to upper
+    Hessenberg form (input preparation at the paper's scale).  Per panel of nb
+    columns, with A0 the matrix at the start of the panel, Q = I - V T V^T the
+    product of the panel's reflectors and Y = A0 V T:
+      column j of the panel is Q_j^T A0 Q_j e_(k+j), formed from A0, Y and V
+      (Q_j the first j reflectors); its reflector extends T and Y (one product
+      A0 v_j per column); after the panel A <- Q^T (A0 - Y V^T) with three
+      matrix products.  Returns the Hessenberg matrix with exact zeros below
+      the subdiagonal; Q is not kept."""
+    import torch
+    A = A.clone()
+    n = A.shape[0]
+    dt, dev = A.dtype, A.device
+    for k0 in range(0, n - 2, nb):
+        b = min(nb, n - 2 - k0)
+        A0 = A
+        V = torch.zeros((n, b), dtype=dt, device=dev)
+        T = torch.zeros((b, b), dtype=dt, device=dev)
+        Y = torch.zeros((n, b), dtype=dt, device=dev)
+        betas = []
+        for j in range(b):
+            c = k0 + j
+            col = A0[:, c].clone()
+            if j > 0:
+                Vj, Tj, Yj = V[:, :j], T[:j, :j], Y[:, :j]
+                col -= Yj @ Vj[c, :]
+                col -= Vj @ (Tj.t() @ (Vj.t() @ col))
+            x = col[c + 1:]
+            alpha = float(x[0])
+            tail = float(torch.linalg.vector_norm(x[1:])) if x.numel() > 1 else 0.0
+            v = torch.zeros(n, dtype=dt, device=dev)
+            v[c + 1] = 1.0
+            if tail == 0.0:
+                tau, beta = 0.0, alpha
+            else:
+                nrm = float(np.hypot(alpha, tail))
+                beta = -nrm if alpha >= 0 else nrm
+                tau = (beta - alpha) / beta
+                v[c + 2:] = x[1:] / (alpha - beta)
+            betas.append(beta)
+            V[:, j] = v
+            if j > 0:
+                T[:j, j] = -tau * (T[:j, :j] @ (V[:, :j].t() @ v))
+            T[j, j] = tau
+            yv = A0[:, c + 1:] @ v[c + 1:]
+            if j > 0:
+                yv = yv - Y[:, :j] @ (V[:, :j].t() @ v)
+            Y[:, j] = tau * yv
+        M = A0 - Y @ V.t()
+        M -= V @ (T.t() @ (V.t() @ M))
+        for j in range(b):
+            c = k0 + j
+            M[c + 2:, c] = 0.0
+            M[c + 1, c] = betas[j]
+        A = M
+        if progress is not None:
+            progress(k0 + b, n)
+    return torch.triu(A, -1)
+
+
 def hessenberg_reduce_torch_batched(A):
     """Unblocked Householder reduction of a stack of square matrices (B, n, n)
     to upper Hessenberg form, vectorized over the stack (input preparation of
@@ -303,9 +364,10 @@ def prescribed_batch_device(count: int, n: int, seed: int = SEED, device="cuda")
     return hessenberg_reduce_torch_batched(A), eigs
 
 
-def prescribed_hessenberg_device(n: int, seed: int = SEED, device="cuda"):
+def prescribed_hessenberg_device(n: int, seed: int = SEED, device="cuda", progress=None):
     """prescribed_hessenberg built on the GPU with torch (Haar W by QR, A = W L W^T,
-    Householder Hessenberg reduction).  Returns (H row-major device tensor, eigenvalues)."""
+    blocked Householder Hessenberg reduction; `progress(done, n)` is called after
+    each panel).  Returns (H row-major device tensor, eigenvalues)."""
     import torch
     g = rng(seed)
     n_pairs = n // 4
@@ -332,5 +394,5 @@ def prescribed_hessenberg_device(n: int, seed: int = SEED, device="cuda"):
             col += 2
     A = WL @ W.t()
     del WL, W
-    H = hessenberg_reduce_torch(A)
+    H = hessenberg_reduce_blocked(A, nb=64, progress=progress)
     return H, eigs_from_spectrum(reals, a, b)

@@ -544,14 +544,9 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
 // line on stderr per top-level AED step, at most one every two seconds.
 void progress_line(int ilo, int kbot, int nd)
 {
-    static int enabled = -1;
     static std::chrono::steady_clock::time_point last;
-    if (enabled < 0) {
-        const char *e = std::getenv("HQR_PROGRESS");
-        enabled = (e && e[0] == '1') ? 1 : 0;
-        last = std::chrono::steady_clock::now() - std::chrono::seconds(10);
-    }
-    if (!enabled) return;
+    const char *e = std::getenv("HQR_PROGRESS");
+    if (!(e && e[0] == '1')) return;
     const auto now = std::chrono::steady_clock::now();
     if (now - last < std::chrono::seconds(2)) return;
     last = now;

@@ -115,16 +115,38 @@ def test_config1_gaussian_n4096(gpu):
         assert res <= 100 * n * U * hn, (idx, w[idx], res)
 
 
+def nearest_both_ways(w, ref):
+    """Largest distance from any computed eigenvalue to the nearest prescribed
+    one and from any prescribed eigenvalue to the nearest computed one (a
+    property test that scales to n = 16384, where an optimal matching does not)."""
+    from scipy.spatial import cKDTree
+    P = np.c_[w.real, w.imag]
+    R = np.c_[ref.real, ref.imag]
+    d1, _ = cKDTree(R).query(P)
+    d2, _ = cKDTree(P).query(R)
+    return max(d1.max(), d2.max())
+
+
 @pytest.mark.skipif(os.environ.get("HQR_FULLSIZE_16K", "0") != "1",
                     reason="n=16384 takes minutes; set HQR_FULLSIZE_16K=1")
 def test_config2_prescribed_n16384(gpu):
     import torch
     n = 16384
     _say("case config2 n=16384 prescribed ns=256 nw=1024 (input built on the GPU)")
-    Hd, ev = hi.prescribed_hessenberg_device(n, seed=2020, device="cuda")
+
+    def prog(done, tot):
+        if done % 2048 == 0 or done >= tot - 2:
+            _say(f"input reduction {done}/{tot}")
+
+    Hd, ev = hi.prescribed_hessenberg_device(n, seed=2020, device="cuda", progress=prog)
     H0 = Hd.clone()
     Hc = Hd.t().contiguous()  # row-major storage of H^T = column-major H
-    Tc, Qc, w, info, st = solve_gpu_colmajor(Hc, {"ns": 256, "nw": 1024})
+    del Hd
+    os.environ["HQR_PROGRESS"] = "1"
+    try:
+        Tc, Qc, w, info, st = solve_gpu_colmajor(Hc, {"ns": 256, "nw": 1024})
+    finally:
+        os.environ.pop("HQR_PROGRESS", None)
     _say(f"stats {st}")
     assert info == 0
     T = Tc.t()
@@ -136,8 +158,10 @@ def test_config2_prescribed_n16384(gpu):
     assert be <= 100 * n * U and ob <= 100 * n * U
     assert torch.all(torch.tril(T, -2) == 0).item()
     wn = w.cpu().numpy()
-    _, _, d = checks.match(wn, ev)
-    assert d.max() <= 1e-10 * hn
+    assert abs(np.sum(wn).real - torch.trace(H0).item()) <= 1e-9 * hn * n
+    d = nearest_both_ways(wn, np.asarray(ev))
+    _say(f"eigenvalues: worst nearest distance {d:.3e}")
+    assert d <= 1e-10 * hn
 
 
 def test_config3_batched_sample(gpu):
