@@ -24,15 +24,22 @@ WORKLOADS = {
 }
 
 
-def make_input(spec, seed):
+def make_input(spec, seed, dev):
+    """Device tensor holding H column-major (row-major storage of H^T)."""
+    import numpy as np
+    import torch
     import hqr_inputs as hi
     n = spec["n"]
+    if spec["gen"] == "prescribed" and n > 4096:
+        H, _ = hi.prescribed_hessenberg_device(n, seed=seed, device=dev)  # host reduction would take minutes
+        return H.t().contiguous()
     if spec["gen"] == "gaussian":
-        return hi.gaussian_hessenberg(n, seed=seed)
-    if spec["gen"] == "hessrand":
-        return hi.hessrand(n, seed=seed)
-    H, _ = hi.prescribed_hessenberg(n, seed=seed)
-    return H
+        H = hi.gaussian_hessenberg(n, seed=seed)
+    elif spec["gen"] == "hessrand":
+        H = hi.hessrand(n, seed=seed)
+    else:
+        H, _ = hi.prescribed_hessenberg(n, seed=seed)
+    return torch.from_numpy(np.ascontiguousarray(H.T)).to(dev)
 
 
 def measured_traffic(kernel):
@@ -57,6 +64,64 @@ def measured_traffic(kernel):
     if h.hexdigest() != rec["sources_sha256"]:
         return None
     return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def batched_run(seed):
+    """Batched form: 20000 Gaussian Hessenberg matrices with orders drawn from
+    16..256, packed, T and Q for each, one call (the second of two timed)."""
+    import ctypes
+    import torch
+    import hqr_inputs as hi
+    from paper_2007_03576_amd._lib import lib
+    dev = torch.device("cuda:0")
+    count = 20000
+    sizes = hi.batched_sizes(count, 16, 256, seed=seed)
+    packed, offs = hi.batched_gaussian(sizes, seed=seed)
+    H0 = torch.from_numpy(packed).to(dev)
+    Q0 = torch.cat([torch.eye(int(n), dtype=torch.float64, device=dev).reshape(-1) for n in sizes])
+    eo = hi.eig_offsets(sizes)
+    d_off, d_n, d_eo = (torch.from_numpy(x).to(dev) for x in (offs, sizes, eo))
+    wr = torch.empty(int(sizes.sum()), dtype=torch.float64, device=dev)
+    wi = torch.empty_like(wr)
+    info = torch.empty(count, dtype=torch.int32, device=dev)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    dt = None
+    for _ in range(2):
+        Hp, Qp = H0.clone(), Q0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc = lib().hqr_schur_batched(P(Hp), P(Qp), P(d_off), P(d_n), count, P(wr), P(wi), P(d_eo), P(info),
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert rc == 0
+    return {"workload": "20000 Gaussian Hessenberg matrices, orders U{16..256} (seeded), T and Q, one call",
+            "s": dt, "solves_per_s": count / dt, "info_max": int(info.abs().max())}
+
+
+def grad_run(seed):
+    """Differentiation form: 512 matrices of order 512 with well-separated
+    prescribed spectra, L = sum softplus(Re l) + 0.1 sum |l|^2, forward Schur
+    solve and backward dL/dH (the second of two timed)."""
+    import torch
+    import hqr_inputs as hi
+    import paper_2007_03576_amd as hq
+    H, _ = hi.prescribed_batch_device(512, 512, seed=seed, device="cuda")
+    fw = bw = None
+    for _ in range(2):
+        X = H.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam = hq.eigvals(X)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = torch.nn.functional.softplus(lam.real).sum() + 0.1 * (lam.abs() ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fw, bw = t1 - t0, t2 - t1
+    return {"workload": "512 matrices n=512, separated prescribed spectra, L = sum softplus(Re l) + 0.1 sum |l|^2",
+            "forward_s": fw, "backward_s": bw, "solves_per_s": 512 / (fw + bw)}
 
 
 def cpu_baseline(spec, seed, target_n):
@@ -88,6 +153,7 @@ def main():
     ap.add_argument("--workload", default="gaussian_hessenberg_n4096", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=2020)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and differentiation lines")
     ap.add_argument("--cpu-n", type=int, default=2048)
     ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--small-shifts", type=int, default=0)
@@ -117,8 +183,7 @@ def main():
     spec = WORKLOADS[args.workload]
     n = spec["n"]
     dev = torch.device("cuda:0")
-    H0 = make_input(spec, args.seed)
-    H0d = torch.from_numpy(np.ascontiguousarray(H0.T)).to(dev)  # row-major of H^T = column-major H
+    H0d = make_input(spec, args.seed, dev)  # row-major of H^T = column-major H
     params = {"ns": spec["ns"], "nw": spec["nw"], "streams": args.streams, "small_shifts": args.small_shifts}
     nsteps = args.warmup + args.steps
     # stage one input copy per step so the timed region is solves only
@@ -148,12 +213,13 @@ def main():
     stats = hq.last_stats()
     dt = (t1 - t0) / args.steps
     assert all(i == 0 for i in infos), infos
-    # accuracy of the last solve (host check, outside the timed region)
-    T = Hs[-1].t().cpu().numpy()
-    Q = Qs[-1].t().cpu().numpy()
+    # accuracy of the last solve (outside the timed region)
+    T = Hs[-1].t()
+    Q = Qs[-1].t()
+    H0 = H0d.t()
     u = 2.0 ** -52
-    be = float(np.linalg.norm(Q.T @ H0 @ Q - T) / np.linalg.norm(H0))
-    orth = float(np.linalg.norm(Q.T @ Q - np.eye(n)))
+    be = float(torch.linalg.norm(Q.t() @ H0 @ Q - T) / torch.linalg.norm(H0))
+    orth = float(torch.linalg.norm(Q.t() @ Q - torch.eye(n, dtype=Q.dtype, device=dev)))
     nominal = 10.0 * n ** 3
     out = {
         "metric": "FP64 TFLOP/s (10n^3 nominal) & Schur solves/sec, batched+grad vs plain, 1 MI355X",
@@ -180,6 +246,10 @@ def main():
         out["roofline"]["traffic"] = measured_traffic(out["roofline"]["kernel"])
     out["kernel_times"] = profiling.summary(prof, args.steps)
     out["kernel_times"]["lds_iteration"]["split"] = lds_split
+    if not args.no_extra:
+        out["plain_solves_per_s"] = 1.0 / dt
+        out["batched"] = batched_run(args.seed)
+        out["grad"] = grad_run(args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.seed, args.cpu_n)
     else:

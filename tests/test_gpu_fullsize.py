@@ -143,11 +143,14 @@ def test_config2_prescribed_n16384(gpu):
     Hc = Hd.t().contiguous()  # row-major storage of H^T = column-major H
     del Hd
     os.environ["HQR_PROGRESS"] = "1"
+    import time
+    t0 = time.perf_counter()
     try:
         Tc, Qc, w, info, st = solve_gpu_colmajor(Hc, {"ns": 256, "nw": 1024})
     finally:
         os.environ.pop("HQR_PROGRESS", None)
-    _say(f"stats {st}")
+    dt = time.perf_counter() - t0
+    _say(f"solve {dt:.1f} s ({10.0 * n ** 3 / dt / 1e12:.3f} TFLOP/s nominal); stats {st}")
     assert info == 0
     T = Tc.t()
     Q = Qc.t()
