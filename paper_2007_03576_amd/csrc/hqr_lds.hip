@@ -34,7 +34,7 @@ struct ReorderState {
     int pos[2][MV], sz[MV], dst[MV]; // moves in flight (ring indexed by move id), position double buffered
     int sj[MV], sm[MV];              // exchange of each lane: first row and order (0: none)
     int roff[MV + 1], coff[MV + 1];  // prefix sums of the row and column work items per lane
-    int head, tail, ns, ilst, halt, chk_done, done, rtot, ctot;
+    int head, tail, ns, ilst, halt, chk_done, done, rtot, ctot, nlanes;
 };
 
 struct SmemCore {
@@ -1558,6 +1558,7 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
             if (lane == 63) {
                 R.rtot = rc;
                 R.ctot = cc;
+                R.nlanes = min(nact + 1, MV); // lanes that can own an exchange this phase
             }
             if (lane == 0) {
                 R.roff[0] = 0;
@@ -1575,12 +1576,14 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
             }
         }
         __syncthreads();
-        const int rtot = R.rtot, ctot = R.ctot;
+        const int rtot = R.rtot, ctot = R.ctot, nl = R.nlanes;
         // left products: rows sj..sj+m-1 over the columns right of the range
         {
             int s = 0;
             for (int it = tid; it < rtot; it += NT) {
-                while (it >= R.roff[s + 1]) ++s;
+                // owner: the number of lanes whose items all precede it (independent loads)
+                s = 0;
+                for (int q = 1; q <= nl; ++q) s += (it >= R.roff[q]) ? 1 : 0;
                 const int j = R.sj[s], m = R.sm[s];
                 const double *G = R.G + s * 16;
                 const int c = j + m + (it - R.roff[s]);
@@ -1605,7 +1608,8 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
         {
             int s = 0;
             for (int it = tid; it < ctot; it += NT) {
-                while (it >= R.coff[s + 1]) ++s;
+                s = 0;
+                for (int q = 1; q <= nl; ++q) s += (it >= R.coff[q]) ? 1 : 0;
                 const int j = R.sj[s], m = R.sm[s];
                 const double *G = R.G + s * 16;
                 const int rr = it - R.coff[s];
@@ -1647,6 +1651,35 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
     const int ns = R.ns;
     __syncthreads();
     return ns;
+}
+
+// v^T x over len entries of x (stride st) with four partial sums, so the
+// multiply-adds form four short dependency chains instead of one long one.
+__device__ __forceinline__ double dot_v(const double *v, const double *x, int64_t st, int len)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = 0;
+    for (; i + 3 < len; i += 4) {
+        s0 = fma(v[i], x[i * st], s0);
+        s1 = fma(v[i + 1], x[(i + 1) * st], s1);
+        s2 = fma(v[i + 2], x[(i + 2) * st], s2);
+        s3 = fma(v[i + 3], x[(i + 3) * st], s3);
+    }
+    for (; i < len; ++i) s0 = fma(v[i], x[i * st], s0);
+    return (s0 + s1) + (s2 + s3);
+}
+
+// x <- x - a v over len entries of x (stride st).
+__device__ __forceinline__ void axpy_v(double a, const double *v, double *x, int64_t st, int len)
+{
+    int i = 0;
+    for (; i + 3 < len; i += 4) {
+        x[i * st] -= a * v[i];
+        x[(i + 1) * st] -= a * v[i + 1];
+        x[(i + 2) * st] -= a * v[i + 2];
+        x[(i + 3) * st] -= a * v[i + 3];
+    }
+    for (; i < len; ++i) x[i * st] -= a * v[i];
 }
 
 // Householder vector of x = vec[0..len-1] (in LDS): overwrites vec with v
@@ -1716,10 +1749,8 @@ __device__ __forceinline__ double restore_lds(Smem &S, double *T, int ldt, int n
         if (tau != 0.0) {
             // left: rows r0..r0+len-1, columns c0..nt-1
             for (int c = c0 + (int)threadIdx.x; c < nt; c += NT) {
-                double s = 0.0;
-                for (int i = 0; i < len; ++i) s += v[i] * T[(r0 + i) + c * ldt];
-                s *= tau;
-                for (int i = 0; i < len; ++i) T[(r0 + i) + c * ldt] -= s * v[i];
+                double *col = T + r0 + c * ldt;
+                axpy_v(tau * dot_v(v, col, 1, len), v, col, 1, len);
             }
             __syncthreads();
             // right: columns r0..r0+len-1 over rows 0..ns-1 of T and all rows of Z
@@ -1733,10 +1764,8 @@ __device__ __forceinline__ double restore_lds(Smem &S, double *T, int ldt, int n
                     M = Z + (it - ns);
                     ld = ldz;
                 }
-                double s = 0.0;
-                for (int i = 0; i < len; ++i) s += M[(r0 + i) * ld] * v[i];
-                s *= tau;
-                for (int i = 0; i < len; ++i) M[(r0 + i) * ld] -= s * v[i];
+                double *row = M + r0 * ld;
+                axpy_v(tau * dot_v(v, row, ld, len), v, row, ld, len);
             }
         }
         __syncthreads();
@@ -2092,11 +2121,8 @@ __global__ void __launch_bounds__(1024) k_restore_global(double *T, int64_t ldt,
         __syncthreads();
         if (tau != 0.0) {
             for (int c = c0 + tid; c < nw; c += nt) {
-                double acc = 0.0;
                 double *col = T + (int64_t)c * ldt + r0;
-                for (int i = 0; i < len; ++i) acc += v[i] * col[i];
-                acc *= tau;
-                for (int i = 0; i < len; ++i) col[i] -= acc * v[i];
+                axpy_v(tau * dot_v(v, col, 1, len), v, col, 1, len);
             }
             __syncthreads();
             for (int it = tid; it < ns + nv; it += nt) {
@@ -2109,10 +2135,8 @@ __global__ void __launch_bounds__(1024) k_restore_global(double *T, int64_t ldt,
                     M = V + (it - ns);
                     l2 = ldv;
                 }
-                double acc = 0.0;
-                for (int i = 0; i < len; ++i) acc += M[(int64_t)(r0 + i) * l2] * v[i];
-                acc *= tau;
-                for (int i = 0; i < len; ++i) M[(int64_t)(r0 + i) * l2] -= acc * v[i];
+                double *row = M + (int64_t)r0 * l2;
+                axpy_v(tau * dot_v(v, row, l2, len), v, row, l2, len);
             }
         }
         __syncthreads();
