@@ -34,7 +34,7 @@ struct ReorderState {
     int pos[2][MV], sz[MV], dst[MV]; // moves in flight (ring indexed by move id), position double buffered
     int sj[MV], sm[MV];              // exchange of each lane: first row and order (0: none)
     int roff[MV + 1], coff[MV + 1];  // prefix sums of the row and column work items per lane
-    int head, tail, ns, ilst, halt, chk_done, done, rtot, ctot, nlanes;
+    int head, tail, ns, ilst, halt, chk_done, done, rtot, ctot;
 };
 
 struct SmemCore {
@@ -1558,7 +1558,6 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
             if (lane == 63) {
                 R.rtot = rc;
                 R.ctot = cc;
-                R.nlanes = min(nact + 1, MV); // lanes that can own an exchange this phase
             }
             if (lane == 0) {
                 R.roff[0] = 0;
@@ -1576,14 +1575,12 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
             }
         }
         __syncthreads();
-        const int rtot = R.rtot, ctot = R.ctot, nl = R.nlanes;
+        const int rtot = R.rtot, ctot = R.ctot;
         // left products: rows sj..sj+m-1 over the columns right of the range
         {
             int s = 0;
             for (int it = tid; it < rtot; it += NT) {
-                // owner: the number of lanes whose items all precede it (independent loads)
-                s = 0;
-                for (int q = 1; q <= nl; ++q) s += (it >= R.roff[q]) ? 1 : 0;
+                while (it >= R.roff[s + 1]) ++s;
                 const int j = R.sj[s], m = R.sm[s];
                 const double *G = R.G + s * 16;
                 const int c = j + m + (it - R.roff[s]);
@@ -1608,8 +1605,7 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
         {
             int s = 0;
             for (int it = tid; it < ctot; it += NT) {
-                s = 0;
-                for (int q = 1; q <= nl; ++q) s += (it >= R.coff[q]) ? 1 : 0;
+                while (it >= R.coff[s + 1]) ++s;
                 const int j = R.sj[s], m = R.sm[s];
                 const double *G = R.G + s * 16;
                 const int rr = it - R.coff[s];
