@@ -68,35 +68,58 @@ def measured_traffic(kernel):
 
 def batched_run(seed):
     """Batched form: 20000 Gaussian Hessenberg matrices with orders drawn from
-    16..256, packed, T and Q for each, one call (the second of two timed)."""
-    import ctypes
+    16..256, packed, T and Q for each.  The solve (order sort, two persistent
+    grids draining a longest-first queue) is captured once into a HIP graph
+    and the second of two replays is timed.  The plain solver (one hqr_schur
+    call per matrix) is timed on a seeded sample of 64 matrices of the same
+    batch for comparison."""
+    import numpy as np
     import torch
     import hqr_inputs as hi
-    from paper_2007_03576_amd._lib import lib
+    import paper_2007_03576_amd as hq
     dev = torch.device("cuda:0")
     count = 20000
     sizes = hi.batched_sizes(count, 16, 256, seed=seed)
-    packed, offs = hi.batched_gaussian(sizes, seed=seed)
+    packed, _ = hi.batched_gaussian(sizes, seed=seed)
     H0 = torch.from_numpy(packed).to(dev)
-    Q0 = torch.cat([torch.eye(int(n), dtype=torch.float64, device=dev).reshape(-1) for n in sizes])
-    eo = hi.eig_offsets(sizes)
-    d_off, d_n, d_eo = (torch.from_numpy(x).to(dev) for x in (offs, sizes, eo))
-    wr = torch.empty(int(sizes.sum()), dtype=torch.float64, device=dev)
-    wi = torch.empty_like(wr)
-    info = torch.empty(count, dtype=torch.int32, device=dev)
-    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    g = hq.BatchedGraph([int(n) for n in sizes])
     dt = None
     for _ in range(2):
-        Hp, Qp = H0.clone(), Q0.clone()
+        g.prob.load(H0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc = lib().hqr_schur_batched(P(Hp), P(Qp), P(d_off), P(d_n), count, P(wr), P(wi), P(d_eo), P(info),
-                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        g.graph.replay()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        assert rc == 0
-    return {"workload": "20000 Gaussian Hessenberg matrices, orders U{16..256} (seeded), T and Q, one call",
-            "s": dt, "solves_per_s": count / dt, "info_max": int(info.abs().max())}
+    info_max = int(g.prob.info.abs().max())
+    # accuracy of a seeded sample (outside the timed region)
+    pick = np.random.default_rng(seed).choice(count, size=32, replace=False)
+    worst_be = worst_orth = 0.0
+    for i in pick:
+        n, o = int(sizes[i]), g.prob.offs[i]
+        A = H0[o:o + n * n].reshape(n, n).t()
+        T = g.prob.H[o:o + n * n].reshape(n, n).t()
+        Q = g.prob.Q[o:o + n * n].reshape(n, n).t()
+        worst_be = max(worst_be, float(torch.linalg.norm(Q.t() @ A @ Q - T) / torch.linalg.norm(A)))
+        worst_orth = max(worst_orth, float(torch.linalg.norm(Q.t() @ Q - torch.eye(n, dtype=Q.dtype, device=dev))))
+    # the plain solver, one call per matrix, on the same sample's first 64 matrices
+    pick = np.random.default_rng(seed + 2).choice(count, size=64, replace=False)
+    mats = [H0[g.prob.offs[i]:g.prob.offs[i] + int(sizes[i]) ** 2].reshape(int(sizes[i]), int(sizes[i])).t()
+            for i in pick]
+    hq.schur(mats[0].t().contiguous().t())  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for A in mats:
+        hq.schur(A)
+    torch.cuda.synchronize()
+    plain_dt = time.perf_counter() - t0
+    plain_rate = len(mats) / plain_dt
+    return {"workload": "20000 Gaussian Hessenberg matrices, orders U{16..256} (seeded), T and Q, one graph replay",
+            "s": dt, "solves_per_s": count / dt, "info_max": info_max,
+            "accuracy_sample32": {"backward_rel_max": worst_be, "orth_max": worst_orth},
+            "plain_per_matrix": {"sample": "64 matrices of the batch, one hqr_schur call each",
+                                 "solves_per_s": plain_rate},
+            "speedup_vs_plain": (count / dt) / plain_rate}
 
 
 def grad_run(seed):
@@ -120,8 +143,19 @@ def grad_run(seed):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         fw, bw = t1 - t0, t2 - t1
+    # the plain solver, one hqr_schur call per matrix (forward only), on 8 of the matrices
+    hq.schur(H[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(8):
+        hq.schur(H[b])
+    torch.cuda.synchronize()
+    plain_rate = 8 / (time.perf_counter() - t0)
     return {"workload": "512 matrices n=512, separated prescribed spectra, L = sum softplus(Re l) + 0.1 sum |l|^2",
-            "forward_s": fw, "backward_s": bw, "solves_per_s": 512 / (fw + bw)}
+            "forward_s": fw, "backward_s": bw, "solves_per_s": 512 / (fw + bw),
+            "plain_per_matrix": {"sample": "8 of the matrices, one hqr_schur call each, forward only",
+                                 "solves_per_s": plain_rate},
+            "speedup_vs_plain": (512 / (fw + bw)) / plain_rate}
 
 
 def cpu_baseline(spec, seed, target_n):

@@ -80,15 +80,25 @@ int hqr_schur(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *w
 int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi, void *stream,
                  const hqr_params *p);
 
-/* Batched form for many small independent problems (persistent launches,
- * one workgroup per matrix).  Matrix i has order n[i], stored packed column
- * major at H + offsets[i] with leading dimension n[i]; Q likewise (Q may be
- * NULL; otherwise it must hold Q0, e.g. identity, on entry, and receives
- * Q0*Qhat).  Orders <= 96 are solved with matrix and factor in LDS, larger
- * ones in place in global memory (the L2-resident path).
+/* Batched form for many small independent problems (the paper's
+ * small-block double-shift Francis solver of Sec. 3.1, `small Schur'), one
+ * workgroup per matrix.  Matrix i has order n[i], stored packed column major at
+ * H + offsets[i] with leading dimension n[i]; Q likewise (Q may be NULL;
+ * otherwise it must hold Q0, e.g. identity, on entry, and receives Q0*Qhat).
+ * Orders <= 96 are solved with matrix and factor in LDS, larger ones in place
+ * in global memory (the L2-resident path).  A counting sort on the device
+ * orders the batch by decreasing order; two persistent grids (global tier,
+ * then LDS tier) take matrices from that queue one at a time, longest first.
+ * Every order runs double-shift steps (hqr_params.small_shifts does not
+ * apply here).  Matrices of order 0 get info 0 and are not touched.
  * Eigenvalues of matrix i go to wr/wi + eig_offsets[i]; info[i] receives the
  * per-matrix code (0 or +i).  offsets, n, eig_offsets, info are device
- * arrays.  Fully asynchronous on `stream`; allocates nothing on the device. */
+ * arrays.  Asynchronous on `stream`.  The queue lives in a buffer the library
+ * keeps per (device, stream): a call with a larger batch than any before on
+ * that stream allocates it (4*(batch+4) bytes), so capture a call into a HIP
+ * graph only after an uncaptured call of at least that batch on that stream.
+ * Calls that overlap on one stream cannot happen; calls on different streams
+ * use different queues.  Returns 0, or -k for a bad argument k. */
 int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int32_t batch,
                       double *wr, double *wi, const int64_t *eig_offsets, int32_t *info, void *stream);
 

@@ -9,7 +9,7 @@ import torch
 from ._lib import HqrError, HqrParams, check, lib
 
 __all__ = ["schur", "schur_colmajor", "schur_batched", "eigvals", "set_params", "params",
-           "last_stats", "HqrError"]
+           "last_stats", "HqrError", "BatchedProblem", "BatchedGraph"]
 
 
 def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
@@ -98,41 +98,99 @@ def schur(H: torch.Tensor, want_q: bool = True, Q0: Optional[torch.Tensor] = Non
     return Hf, Qf, w, info
 
 
+class BatchedProblem:
+    """Device buffers of one packing of the batched form: matrices of the given
+    orders stored back to back column major (offsets = running sums of n^2),
+    Q (identity on entry) likewise, eigenvalue slots (offsets = running sums
+    of n) and per-matrix info."""
+
+    def __init__(self, sizes: Sequence[int], want_q: bool = True, device="cuda"):
+        dev = torch.device(device)
+        self.sizes = [int(s) for s in sizes]
+        offs, eoffs = [0], [0]
+        for s in self.sizes[:-1]:
+            offs.append(offs[-1] + s * s)
+            eoffs.append(eoffs[-1] + s)
+        self.offs, self.eoffs = offs, eoffs
+        tot2 = sum(s * s for s in self.sizes)
+        self.H = torch.zeros(max(tot2, 1), dtype=torch.float64, device=dev)
+        self.Q = torch.zeros_like(self.H) if want_q else None
+        self.Q0 = None
+        if want_q:
+            self.Q0 = torch.cat([torch.eye(s, dtype=torch.float64, device=dev).reshape(-1)
+                                 for s in self.sizes]) if self.sizes else torch.zeros(1, dtype=torch.float64,
+                                                                                       device=dev)
+        self.d_off = torch.tensor(offs, dtype=torch.int64, device=dev)
+        self.d_n = torch.tensor(self.sizes, dtype=torch.int32, device=dev)
+        self.d_eo = torch.tensor(eoffs, dtype=torch.int64, device=dev)
+        tot = sum(self.sizes)
+        self.wr = torch.empty(max(tot, 1), dtype=torch.float64, device=dev)
+        self.wi = torch.empty_like(self.wr)
+        self.info = torch.empty(len(self.sizes), dtype=torch.int32, device=dev)
+
+    def load(self, packed: torch.Tensor) -> None:
+        """Copy packed inputs in (and Q0 = I) on the current stream."""
+        self.H[:packed.numel()].copy_(packed)
+        if self.Q is not None:
+            self.Q.copy_(self.Q0)
+
+    def solve(self, stream=None) -> None:
+        P = lambda t: ctypes.c_void_p(t.data_ptr())
+        rc = lib().hqr_schur_batched(P(self.H), P(self.Q) if self.Q is not None else None, P(self.d_off),
+                                     P(self.d_n), len(self.sizes), P(self.wr), P(self.wi), P(self.d_eo),
+                                     P(self.info), _stream_handle(stream))
+        check(rc, "hqr_schur_batched")
+
+    def results(self):
+        Ts, Qs, ws = [], [], []
+        for s, o, eo in zip(self.sizes, self.offs, self.eoffs):
+            Ts.append(self.H[o:o + s * s].reshape(s, s).t())
+            Qs.append(self.Q[o:o + s * s].reshape(s, s).t() if self.Q is not None else None)
+            ws.append(torch.complex(self.wr[eo:eo + s], self.wi[eo:eo + s]))
+        return Ts, Qs, ws, self.info
+
+
+class BatchedGraph:
+    """The batched solve of one packing captured once into a HIP graph
+    (through torch.cuda.CUDAGraph) and replayed: run() copies new inputs into
+    the captured buffers, replays, and returns the buffers.  The library's
+    work queue for the capture stream is allocated by an uncaptured warm-up
+    solve before capture."""
+
+    def __init__(self, sizes: Sequence[int], want_q: bool = True, device="cuda"):
+        self.prob = BatchedProblem(sizes, want_q, device)
+        self.stream = torch.cuda.Stream(device=device)
+        self.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.stream):
+            if self.prob.Q is not None:
+                self.prob.Q.copy_(self.prob.Q0)
+            self.prob.solve()  # warm-up: queue buffer and kernel attributes
+        self.stream.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=self.stream, capture_error_mode="relaxed"):
+            self.prob.solve()
+
+    def run(self, packed: torch.Tensor):
+        self.prob.load(packed)
+        self.graph.replay()
+        return self.prob.results()
+
+
+def pack(mats: Sequence[torch.Tensor]) -> torch.Tensor:
+    """Column-major packing of square matrices back to back."""
+    return torch.cat([m.t().contiguous().reshape(-1) for m in mats]).to(torch.float64)
+
+
 def schur_batched(mats: Sequence[torch.Tensor], want_q: bool = True, stream=None):
-    """Batched form: list of square Hessenberg matrices (orders <= 96) on one device.
-    Returns (list of T, list of Q or None, list of w, info tensor)."""
+    """Batched form: list of square Hessenberg matrices of any orders on one
+    device.  Returns (list of T, list of Q or None, list of w, info tensor)."""
     dev = mats[0].device
-    sizes = [int(m.shape[0]) for m in mats]
-    offs = [0]
-    for s in sizes[:-1]:
-        offs.append(offs[-1] + s * s)
-    eoffs = [0]
-    for s in sizes[:-1]:
-        eoffs.append(eoffs[-1] + s)
-    packed = torch.cat([m.t().contiguous().reshape(-1) for m in mats]).to(torch.float64)
-    Qp = None
-    if want_q:
-        Qp = torch.cat([torch.eye(s, dtype=torch.float64, device=dev).reshape(-1) for s in sizes])
-    d_off = torch.tensor(offs, dtype=torch.int64, device=dev)
-    d_n = torch.tensor(sizes, dtype=torch.int32, device=dev)
-    d_eo = torch.tensor(eoffs, dtype=torch.int64, device=dev)
-    tot = sum(sizes)
-    wr = torch.empty(max(tot, 1), dtype=torch.float64, device=dev)
-    wi = torch.empty_like(wr)
-    info = torch.empty(len(mats), dtype=torch.int32, device=dev)
-    rc = lib().hqr_schur_batched(ctypes.c_void_p(packed.data_ptr()),
-                                 ctypes.c_void_p(Qp.data_ptr()) if Qp is not None else None,
-                                 ctypes.c_void_p(d_off.data_ptr()), ctypes.c_void_p(d_n.data_ptr()),
-                                 len(mats), ctypes.c_void_p(wr.data_ptr()), ctypes.c_void_p(wi.data_ptr()),
-                                 ctypes.c_void_p(d_eo.data_ptr()), ctypes.c_void_p(info.data_ptr()),
-                                 _stream_handle(stream))
-    check(rc, "hqr_schur_batched")
-    Ts, Qs, ws = [], [], []
-    for s, o, eo in zip(sizes, offs, eoffs):
-        Ts.append(packed[o:o + s * s].reshape(s, s).t())
-        Qs.append(Qp[o:o + s * s].reshape(s, s).t() if Qp is not None else None)
-        ws.append(torch.complex(wr[eo:eo + s], wi[eo:eo + s]))
-    return Ts, Qs, ws, info
+    prob = BatchedProblem([int(m.shape[0]) for m in mats], want_q, dev)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(s):
+        prob.load(pack(mats))
+    prob.solve(s)
+    return prob.results()
 
 
 def eigvals(H: torch.Tensor) -> torch.Tensor:

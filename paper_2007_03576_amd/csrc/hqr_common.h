@@ -116,8 +116,11 @@ hipError_t launch_check_finite(const double *H, int64_t ld, int n, int *flag, hi
 hipError_t launch_zero_lower(double *H, int64_t ld, int n, hipStream_t s);
 hipError_t launch_transpose_pad(const double *V, int64_t ldv, int K, double *Ut, int K16,
                                 hipStream_t s);
+// Work queue of the batched form: QHDR header ints, then the matrix indices
+// in order of decreasing order n (longest first).
+constexpr int QHDR = 4;
 hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch,
-                          double *wr, double *wi, const int64_t *eoff, int32_t *info, int nsmall,
+                          double *wr, double *wi, const int64_t *eoff, int32_t *info, int32_t *queue,
                           hipStream_t s);
 hipError_t launch_eig_backward(const double *T, const double *Q, int n, int batch, const double *wr,
                                const double *wi, const double *gwr, const double *gwi, double *dH,

@@ -23,7 +23,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 using namespace hqr;
@@ -32,6 +34,14 @@ namespace {
 
 std::mutex g_mu;
 hqr_params g_params = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0.0, 0, 0};
+
+// Work-queue buffers of the batched form, one per (device, stream), grown on
+// demand and kept until the process ends.
+struct QueueBuf {
+    int32_t *p = nullptr;
+    int64_t cap = 0;
+};
+std::map<std::pair<int, void *>, QueueBuf> g_queues;
 thread_local int64_t t_stats[8];
 
 struct Params {
@@ -1043,6 +1053,13 @@ int hqr_finalize(void)
         }
         W = Workspace();
     }
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_queues) {
+        hipSetDevice(kv.first.first);
+        hipDeviceSynchronize();
+        hipFree(kv.second.p);
+    }
+    g_queues.clear();
     return 0;
 }
 
@@ -1058,15 +1075,29 @@ int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_
     if (!wi) return -7;
     if (!eig_offsets) return -8;
     if (!info) return -9;
-    hqr_params gp;
+    int32_t *queue = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        gp = g_params;
+        int dev = 0;
+        CK(hipGetDevice(&dev));
+        QueueBuf &qb = g_queues[std::make_pair(dev, stream)];
+        const int64_t need = (int64_t)batch + QHDR;
+        if (qb.cap < need) {
+            if (qb.p) {
+                CK(hipStreamSynchronize((hipStream_t)stream)); // earlier calls on this stream still read it
+                CK(hipFree(qb.p));
+            }
+            qb.p = nullptr;
+            qb.cap = 0;
+            CK(hipMalloc((void **)&qb.p, need * sizeof(int32_t)));
+            qb.cap = need;
+        }
+        queue = qb.p;
     }
-    int nsmall = gp.small_shifts > 0 ? std::min(gp.small_shifts, 16) & ~1 : 2;
-    CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, nsmall, (hipStream_t)stream));
+    CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, queue, (hipStream_t)stream));
     return 0;
 }
+
 
 int hqr_eig_backward_batched(const double *T, const double *Q, int32_t n, int32_t batch, const double *wr,
                              const double *wi, const double *gwr, const double *gwi, double *dH, int32_t hess_mask,

@@ -21,6 +21,9 @@
 #include <algorithm>
 #include <cfloat>
 #include <climits>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 namespace hqr {
 
@@ -2296,11 +2299,21 @@ __global__ void k_transpose_pad(const double *V, int64_t ldv, int K, double *Ut,
 static_assert(sizeof(Smem) <= 160 * 1024, "the LDS kernels need one workgroup's 160 KB of LDS at most");
 static size_t smem_bytes() { return sizeof(Smem); }
 
+// Dynamic-LDS limit of an LDS kernel, set once per (kernel, device) so that
+// later launches (also under stream capture) make no attribute call.
 static hipError_t prep(const void *fn)
 {
-    static bool done[8] = {false};
-    (void)done;
-    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_bytes());
+    static std::mutex mu;
+    static std::vector<std::pair<const void *, int>> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    for (const auto &d : done)
+        if (d.first == fn && d.second == dev) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_bytes());
+    if (e == hipSuccess) done.emplace_back(fn, dev);
+    return e;
 }
 
 hipError_t launch_iter(double *H, int64_t ld, int n, int ilo, int kbot, int nw, int nmin, double smlnum,
@@ -2404,22 +2417,119 @@ hipError_t launch_finalize_ws(double *H, int64_t ld, int n, double *Q, double *w
 }
 
 // ---------------------------------------------------------------------------
-// batched form: one workgroup per matrix, persistent grid
+// batched form: persistent grids fed from a work queue, one workgroup per matrix
 
+// Eigenvalues of a finished quasi-triangular matrix (2x2 blocks standardized):
+// one thread walks the diagonal.
+__device__ void batched_eigs(const double *A, int lda, int n, double *er, double *ei)
+{
+    int k = 0;
+    while (k < n) {
+        bool two = (k + 1 < n && A[(k + 1) + (int64_t)k * lda] != 0.0);
+        if (!two) {
+            er[k] = A[k + (int64_t)k * lda];
+            ei[k] = 0.0;
+            k += 1;
+        } else {
+            double r1, i1, r2, i2;
+            eig2x2(A[k + (int64_t)k * lda], A[k + (int64_t)(k + 1) * lda], A[(k + 1) + (int64_t)k * lda],
+                   A[(k + 1) + (int64_t)(k + 1) * lda], r1, i1, r2, i2);
+            if (i1 < 0.0) {
+                double t = i1;
+                i1 = i2;
+                i2 = t;
+            }
+            er[k] = r1;
+            ei[k] = i1;
+            er[k + 1] = r2;
+            ei[k + 1] = i2;
+            k += 2;
+        }
+    }
+}
+
+// Next queue position for this workgroup (one atomic per matrix, broadcast
+// through LDS).
+__device__ __forceinline__ int queue_next(SmemCore &S, int32_t *head)
+{
+    if (threadIdx.x == 0) S.ic[7] = atomicAdd(head, 1);
+    __syncthreads();
+    const int k = S.ic[7];
+    __syncthreads();
+    return k;
+}
+
+constexpr int QBINS = 4096;
+constexpr int QNT = 1024;
+__device__ __forceinline__ int order_bin(int n) { return n <= 0 ? 0 : min(n, QBINS - 1); }
+
+// Longest-first order of the batch: counting sort of the orders (one
+// workgroup, bins in LDS), then the queue heads: q[0] = 0 for the global
+// tier (positions [0, q[2])), q[1] = q[2] = number of orders above the LDS
+// limit for the LDS tier (positions [q[2], q[3])), q[3] = number of positive
+// orders.  Empty matrices (order <= 0, sorted last) are finished here.
+__global__ void __launch_bounds__(QNT) k_batched_order(const int32_t *nn, int batch, int32_t *q, int32_t *info)
+{
+    __shared__ int cnt[QBINS];
+    __shared__ int part[QNT];
+    const int tid = threadIdx.x;
+    for (int b = tid; b < QBINS; b += QNT) cnt[b] = 0;
+    __syncthreads();
+    for (int i = tid; i < batch; i += QNT) atomicAdd(&cnt[order_bin(nn[i])], 1);
+    __syncthreads();
+    // thread t owns the four bins QBINS-1-4t .. QBINS-4-4t (counted from the top)
+    int own = 0;
+    for (int k = 0; k < 4; ++k) own += cnt[QBINS - 1 - (4 * tid + k)];
+    part[tid] = own;
+    __syncthreads();
+    for (int off = 1; off < QNT; off <<= 1) {
+        int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int base = part[tid] - own; // items in higher bins
+    for (int k = 0; k < 4; ++k) {
+        const int b = QBINS - 1 - (4 * tid + k);
+        const int c = cnt[b];
+        cnt[b] = base;
+        base += c;
+    }
+    __syncthreads();
+    const int nbig = cnt[MMAX]; // start of bin MMAX = number of orders above MMAX
+    const int npos = cnt[0];    // start of bin 0 = number of positive orders
+    __syncthreads();
+    int32_t *order = q + QHDR;
+    for (int i = tid; i < batch; i += QNT) {
+        const int pos = atomicAdd(&cnt[order_bin(nn[i])], 1);
+        order[pos] = i;
+        if (nn[i] <= 0) info[i] = 0;
+    }
+    if (tid == 0) {
+        q[0] = 0;
+        q[1] = nbig;
+        q[2] = nbig;
+        q[3] = npos;
+    }
+}
+
+// Orders up to the LDS limit: double-shift solver with matrix and factor in
+// LDS.  Bulge chains (more than 2 shifts) are switched off in the batched
+// kernels: runs with them did not finish and the cause is not yet known.
 __global__ void __launch_bounds__(NT) k_batched(double *H, double *Q, const int64_t *offs, const int32_t *nn,
                                                 int batch, double *wr, double *wi, const int64_t *eoff,
-                                                int32_t *info, int nsmall)
+                                                int32_t *info, int32_t *q)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem &S = *reinterpret_cast<Smem *>(smem_raw);
     const int tid = threadIdx.x;
-    for (int b = blockIdx.x; b < batch; b += gridDim.x) {
+    const int32_t *order = q + QHDR;
+    const int npos = q[3];
+    for (;;) {
+        const int k = queue_next(S, &q[1]);
+        if (k >= npos) break;
+        const int b = order[k];
         const int n = nn[b];
-        if (n > MMAX) continue; // global tier
-        if (n <= 0) {
-            if (tid == 0) info[b] = 0;
-            continue;
-        }
         double *A = H + offs[b];
         for (int it = tid; it < n * n; it += NT) {
             int r = it % n, c = it / n;
@@ -2428,37 +2538,14 @@ __global__ void __launch_bounds__(NT) k_batched(double *H, double *Q, const int6
         identity_lds(S.Z, LDM, n, n);
         __syncthreads();
         const double smlnum = DBL_MIN * ((double)n / kU);
-        int inf = qr_small(S, S.A, LDM, n, S.Z, LDM, n, smlnum, 0, nsmall);
+        int inf = qr_small(S, S.A, LDM, n, S.Z, LDM, n, smlnum, 0, 2);
         __syncthreads();
         for (int it = tid; it < n * n; it += NT) {
             int r = it % n, c = it / n;
             A[it] = (r <= c + 1) ? S.A[r + c * LDM] : 0.0;
         }
         if (tid == 0) {
-            double *er = wr + eoff[b], *ei = wi + eoff[b];
-            int k = 0;
-            while (k < n) {
-                bool two = (k + 1 < n && S.A[(k + 1) + k * LDM] != 0.0);
-                if (!two) {
-                    er[k] = S.A[k + k * LDM];
-                    ei[k] = 0.0;
-                    k += 1;
-                } else {
-                    double r1, i1, r2, i2;
-                    eig2x2(S.A[k + k * LDM], S.A[k + (k + 1) * LDM], S.A[(k + 1) + k * LDM],
-                           S.A[(k + 1) + (k + 1) * LDM], r1, i1, r2, i2);
-                    if (i1 < 0.0) {
-                        double t = i1;
-                        i1 = i2;
-                        i2 = t;
-                    }
-                    er[k] = r1;
-                    ei[k] = i1;
-                    er[k + 1] = r2;
-                    ei[k + 1] = i2;
-                    k += 2;
-                }
-            }
+            batched_eigs(S.A, LDM, n, wr + eoff[b], wi + eoff[b]);
             info[b] = inf;
         }
         __syncthreads();
@@ -2473,7 +2560,7 @@ __global__ void __launch_bounds__(NT) k_batched(double *H, double *Q, const int6
             for (int it = tid; it < n * n; it += NT) {
                 int r = it % n, c = it / n;
                 double acc = 0.0;
-                for (int k = 0; k < n; ++k) acc += S.A[r + k * LDM] * S.Z[k + c * LDM];
+                for (int kk = 0; kk < n; ++kk) acc += S.A[r + kk * LDM] * S.Z[kk + c * LDM];
                 Qb[it] = acc;
             }
         }
@@ -2481,17 +2568,21 @@ __global__ void __launch_bounds__(NT) k_batched(double *H, double *Q, const int6
     }
 }
 
-// Orders above the LDS limit: the same solver with the matrix and Q in global
-// memory (L2 resident); small LDS footprint, two workgroups per CU.
+// Orders above the LDS limit: the double-shift solver with the matrix and Q
+// in global memory (L2 resident); small LDS footprint, two workgroups per CU.
 __global__ void __launch_bounds__(NT) k_batched_global(double *H, double *Q, const int64_t *offs,
                                                        const int32_t *nn, int batch, double *wr, double *wi,
-                                                       const int64_t *eoff, int32_t *info, int nsmall)
+                                                       const int64_t *eoff, int32_t *info, int32_t *q)
 {
     __shared__ SmemCore S;
     const int tid = threadIdx.x;
-    for (int b = blockIdx.x; b < batch; b += gridDim.x) {
+    const int32_t *order = q + QHDR;
+    const int nbig = q[2];
+    for (;;) {
+        const int k = queue_next(S, &q[0]);
+        if (k >= nbig) break;
+        const int b = order[k];
         const int n = nn[b];
-        if (n <= MMAX) continue;
         double *A = H + offs[b];
         for (int it = tid; it < n * n; it += NT) {
             int r = it % n, c = it / n;
@@ -2500,33 +2591,10 @@ __global__ void __launch_bounds__(NT) k_batched_global(double *H, double *Q, con
         double *Z = Q ? Q + offs[b] : A; // without Q: no Z rows (nz = 0)
         __syncthreads();
         const double smlnum = DBL_MIN * ((double)n / kU);
-        int inf = qr_small(S, A, n, n, Z, n, Q ? n : 0, smlnum, 0, nsmall);
+        int inf = qr_small(S, A, n, n, Z, n, Q ? n : 0, smlnum, 0, 2);
         __syncthreads();
         if (tid == 0) {
-            double *er = wr + eoff[b], *ei = wi + eoff[b];
-            int k = 0;
-            while (k < n) {
-                bool two = (k + 1 < n && A[(k + 1) + (int64_t)k * n] != 0.0);
-                if (!two) {
-                    er[k] = A[k + (int64_t)k * n];
-                    ei[k] = 0.0;
-                    k += 1;
-                } else {
-                    double r1, i1, r2, i2;
-                    eig2x2(A[k + (int64_t)k * n], A[k + (int64_t)(k + 1) * n], A[(k + 1) + (int64_t)k * n],
-                           A[(k + 1) + (int64_t)(k + 1) * n], r1, i1, r2, i2);
-                    if (i1 < 0.0) {
-                        double t = i1;
-                        i1 = i2;
-                        i2 = t;
-                    }
-                    er[k] = r1;
-                    ei[k] = i1;
-                    er[k + 1] = r2;
-                    ei[k + 1] = i2;
-                    k += 2;
-                }
-            }
+            batched_eigs(A, n, n, wr + eoff[b], wi + eoff[b]);
             info[b] = inf;
         }
         __syncthreads();
@@ -2534,19 +2602,21 @@ __global__ void __launch_bounds__(NT) k_batched_global(double *H, double *Q, con
 }
 
 hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch, double *wr,
-                          double *wi, const int64_t *eoff, int32_t *info, int nsmall, hipStream_t s)
+                          double *wi, const int64_t *eoff, int32_t *info, int32_t *queue, hipStream_t s)
 {
     hipError_t e = prep((const void *)k_batched);
     if (e != hipSuccess) return e;
     int dev = 0, ncu = 256;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    int grid = std::min(batch, std::max(ncu, 1));
-    // orders > MMAX first (they dominate the time), then the LDS tier
-    hipLaunchKernelGGL(k_batched_global, dim3(std::min(batch, 2 * std::max(ncu, 1))), dim3(NT), 0, s, H, Q,
-                       offsets, n, batch, wr, wi, eoff, info, nsmall);
-    hipLaunchKernelGGL(k_batched, dim3(grid), dim3(NT), smem_bytes(), s, H, Q, offsets, n, batch, wr, wi, eoff,
-                       info, nsmall);
+    ncu = std::max(ncu, 1);
+    hipLaunchKernelGGL(k_batched_order, dim3(1), dim3(QNT), 0, s, n, batch, queue, info);
+    // orders > MMAX first (they dominate the time), then the LDS tier; each
+    // grid drains its queue longest-first
+    hipLaunchKernelGGL(k_batched_global, dim3(std::min(batch, 2 * ncu)), dim3(NT), 0, s, H, Q, offsets, n, batch,
+                       wr, wi, eoff, info, queue);
+    hipLaunchKernelGGL(k_batched, dim3(std::min(batch, ncu)), dim3(NT), smem_bytes(), s, H, Q, offsets, n, batch,
+                       wr, wi, eoff, info, queue);
     return hipGetLastError();
 }
 

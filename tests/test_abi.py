@@ -60,3 +60,4 @@ def test_params_roundtrip_and_rejection(L):
     assert L.hqr_set_params(ctypes.byref(bad)) == -1
     assert L.hqr_set_params(ctypes.byref(old)) == 0
     assert L.hqr_set_params(None) == -1
+

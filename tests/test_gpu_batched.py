@@ -67,3 +67,93 @@ def test_batched_prescribed_spectra(gpu):
         _, _, d = checks.match(w, evs[i])
         assert d.max() <= 1e-10 * np.linalg.norm(H)
         check_one(H, Ts[i].cpu().numpy(), Qs[i].cpu().numpy(), w, int(info[i]), f"p{i}")
+
+
+def _packed_case(lo, hi_, count, seed):
+    import torch
+    sizes = hi.batched_sizes(count, lo, hi_, seed=seed)
+    mats = [hi.gaussian_hessenberg(int(n), seed=seed * 1000 + i) for i, n in enumerate(sizes)]
+    return mats, [torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in mats]
+
+
+@pytest.mark.skip(reason="per-bucket shift counts (bulge chains in the batched kernels) did not finish on the "
+                         "GPU, cause not found; the table was removed and the batched kernels run double shifts")
+def test_batched_shift_table_both_tiers(gpu):
+    """Per-bucket shift counts (multishift bulge chains in the LDS and the
+    global-memory tiers), longest-first queue over mixed orders incl. 0."""
+    import torch
+    import paper_2007_03576_amd as hq
+    _say("case batched shift table 32:2,64:4,96:6,160:8,256:12 sizes 0..200")
+    hq.set_batched_shifts([32, 64, 96, 160, 256], [2, 4, 6, 8, 12])  # entry point removed
+    try:
+        mats, _ = _packed_case(1, 200, 24, 11)
+        mats = mats[:12] + [np.zeros((0, 0))] + mats[12:]
+        dev = [torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in mats]
+        Ts, Qs, ws, info = hq.schur_batched(dev)
+        torch.cuda.synchronize()
+        info = info.cpu().numpy()
+        for i, H in enumerate(mats):
+            if H.shape[0] == 0:
+                assert info[i] == 0
+                continue
+            check_one(H, Ts[i].cpu().numpy(), Qs[i].cpu().numpy(), ws[i].cpu().numpy(), int(info[i]),
+                      f"t{i} n={H.shape[0]}")
+    finally:
+        hq.set_batched_shifts([], [])
+
+
+@pytest.mark.skip(reason="per-bucket shift counts (bulge chains in the batched kernels) did not finish on the "
+                         "GPU, cause not found; the table was removed and the batched kernels run double shifts")
+def test_batched_shift_table_lds_tier(gpu):
+    """Per-bucket shift counts in the LDS tier (bulge chains of 2..6 bulges),
+    double shifts above it, longest-first queue over mixed orders incl. 0."""
+    import torch
+    import paper_2007_03576_amd as hq
+    _say("case batched shift table 24:2,48:4,72:8,96:12 sizes 1..160 plus an empty matrix")
+    hq.set_batched_shifts([24, 48, 72, 96], [2, 4, 8, 12])
+    try:
+        mats, _ = _packed_case(1, 160, 24, 13)
+        mats = mats[:12] + [np.zeros((0, 0))] + mats[12:]
+        dev = [torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in mats]
+        Ts, Qs, ws, info = hq.schur_batched(dev)
+        torch.cuda.synchronize()
+        info = info.cpu().numpy()
+        for i, H in enumerate(mats):
+            if H.shape[0] == 0:
+                assert info[i] == 0
+                continue
+            check_one(H, Ts[i].cpu().numpy(), Qs[i].cpu().numpy(), ws[i].cpu().numpy(), int(info[i]),
+                      f"t{i} n={H.shape[0]}")
+    finally:
+        hq.set_batched_shifts([], [])
+
+
+def test_batched_graph_replays_match_eager(gpu):
+    """The batched solve captured into a HIP graph: three replays on new
+    inputs, eager work and synchronizations between them, each bit-identical
+    to an eager solve of the same input."""
+    import torch
+    import paper_2007_03576_amd as hq
+    from paper_2007_03576_amd.api import pack
+    _say("case batched graph replay sizes 16..140 count 40")
+    sizes = hi.batched_sizes(40, 16, 140, seed=21)
+    g = hq.BatchedGraph([int(n) for n in sizes])
+    for rep in range(3):
+        mats = [hi.gaussian_hessenberg(int(n), seed=7000 + 100 * rep + i) for i, n in enumerate(sizes)]
+        packed = pack([torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in mats])
+        Ts, Qs, ws, info = g.run(packed)
+        torch.cuda.synchronize()
+        got_T = g.prob.H.clone()
+        got_Q = g.prob.Q.clone()
+        got_w = (g.prob.wr.clone(), g.prob.wi.clone())
+        assert int(info.abs().max()) == 0
+        eager = hq.BatchedProblem([int(n) for n in sizes])
+        eager.load(packed)
+        eager.solve()
+        torch.cuda.synchronize()
+        assert torch.equal(eager.H, got_T), f"replay {rep}: T differs from eager"
+        assert torch.equal(eager.Q, got_Q), f"replay {rep}: Q differs from eager"
+        assert torch.equal(eager.wr, got_w[0]) and torch.equal(eager.wi, got_w[1])
+        k = rep * 7 % len(mats)
+        check_one(mats[k], Ts[k].cpu().numpy(), Qs[k].cpu().numpy(), ws[k].cpu().numpy(), 0, f"rep{rep} m{k}")
+
