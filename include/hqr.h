@@ -88,14 +88,15 @@ int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double
  * Orders <= 96 are solved with matrix and factor in LDS, larger ones in place
  * in global memory (the L2-resident path).  A counting sort on the device
  * orders the batch by decreasing order; two persistent grids (global tier,
- * then LDS tier) take matrices from that queue one at a time, longest first.
+ * then LDS tier) take matrices from that queue one at a time, longest first;
+ * orders above 320 go to half of the global grid only (cache footprint).
  * Every order runs double-shift steps (hqr_params.small_shifts does not
  * apply here).  Matrices of order 0 get info 0 and are not touched.
  * Eigenvalues of matrix i go to wr/wi + eig_offsets[i]; info[i] receives the
  * per-matrix code (0 or +i).  offsets, n, eig_offsets, info are device
  * arrays.  Asynchronous on `stream`.  The queue lives in a buffer the library
  * keeps per (device, stream): a call with a larger batch than any before on
- * that stream allocates it (4*(batch+4) bytes), so capture a call into a HIP
+ * that stream allocates it (4*(batch+8) bytes), so capture a call into a HIP
  * graph only after an uncaptured call of at least that batch on that stream.
  * Calls that overlap on one stream cannot happen; calls on different streams
  * use different queues.  Returns 0, or -k for a bad argument k. */

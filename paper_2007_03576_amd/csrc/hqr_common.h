@@ -118,7 +118,7 @@ hipError_t launch_transpose_pad(const double *V, int64_t ldv, int K, double *Ut,
                                 hipStream_t s);
 // Work queue of the batched form: QHDR header ints, then the matrix indices
 // in order of decreasing order n (longest first).
-constexpr int QHDR = 4;
+constexpr int QHDR = 8;
 hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch,
                           double *wr, double *wi, const int64_t *eoff, int32_t *info, int32_t *queue,
                           hipStream_t s);

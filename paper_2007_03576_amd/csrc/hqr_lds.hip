@@ -2459,15 +2459,24 @@ __device__ __forceinline__ int queue_next(SmemCore &S, int32_t *head)
     return k;
 }
 
+// Orders above WIDE_N go only to the lower half of the global-memory grid
+// (about one workgroup per CU).  Per bulge position a workgroup touches
+// about 176*n bytes of H and Q (n cache lines for three rows, three columns
+// of H and Q); two workgroups per CU keep that inside the CU's share of L2
+// (4 MB per 32 CUs) up to about n = 360, and one does up to about 700.
+constexpr int WIDE_N = 320;
+
 constexpr int QBINS = 4096;
 constexpr int QNT = 1024;
 __device__ __forceinline__ int order_bin(int n) { return n <= 0 ? 0 : min(n, QBINS - 1); }
 
 // Longest-first order of the batch: counting sort of the orders (one
-// workgroup, bins in LDS), then the queue heads: q[0] = 0 for the global
-// tier (positions [0, q[2])), q[1] = q[2] = number of orders above the LDS
-// limit for the LDS tier (positions [q[2], q[3])), q[3] = number of positive
-// orders.  Empty matrices (order <= 0, sorted last) are finished here.
+// workgroup, bins in LDS), then the queue heads: q[0] = 0 for the orders
+// above WIDE_N (positions [0, q[5])), q[4] = q[5] for the other orders of
+// the global tier (positions [q[5], q[2])), q[1] = q[2] = number of orders
+// above the LDS limit for the LDS tier (positions [q[2], q[3])), q[3] =
+// number of positive orders.  Empty matrices (order <= 0, sorted last) are
+// finished here.
 __global__ void __launch_bounds__(QNT) k_batched_order(const int32_t *nn, int batch, int32_t *q, int32_t *info)
 {
     __shared__ int cnt[QBINS];
@@ -2496,8 +2505,9 @@ __global__ void __launch_bounds__(QNT) k_batched_order(const int32_t *nn, int ba
         base += c;
     }
     __syncthreads();
-    const int nbig = cnt[MMAX]; // start of bin MMAX = number of orders above MMAX
-    const int npos = cnt[0];    // start of bin 0 = number of positive orders
+    const int nbig = cnt[MMAX];   // start of bin MMAX = number of orders above MMAX
+    const int nwide = cnt[WIDE_N]; // number of orders above WIDE_N
+    const int npos = cnt[0];      // start of bin 0 = number of positive orders
     __syncthreads();
     int32_t *order = q + QHDR;
     for (int i = tid; i < batch; i += QNT) {
@@ -2510,6 +2520,8 @@ __global__ void __launch_bounds__(QNT) k_batched_order(const int32_t *nn, int ba
         q[1] = nbig;
         q[2] = nbig;
         q[3] = npos;
+        q[4] = nwide;
+        q[5] = nwide;
     }
 }
 
@@ -2577,10 +2589,22 @@ __global__ void __launch_bounds__(NT) k_batched_global(double *H, double *Q, con
     __shared__ SmemCore S;
     const int tid = threadIdx.x;
     const int32_t *order = q + QHDR;
-    const int nbig = q[2];
+    const int nbig = q[2], nwide = q[5];
+    // the lower half of the grid takes the orders above WIDE_N first, then
+    // joins the upper half on the rest
+    bool wide = blockIdx.x < (gridDim.x + 1) / 2 && nwide > 0;
     for (;;) {
-        const int k = queue_next(S, &q[0]);
-        if (k >= nbig) break;
+        int k;
+        if (wide) {
+            k = queue_next(S, &q[0]);
+            if (k >= nwide) {
+                wide = false;
+                continue;
+            }
+        } else {
+            k = queue_next(S, &q[4]);
+            if (k >= nbig) break;
+        }
         const int b = order[k];
         const int n = nn[b];
         double *A = H + offs[b];

@@ -157,3 +157,19 @@ def test_batched_graph_replays_match_eager(gpu):
         k = rep * 7 % len(mats)
         check_one(mats[k], Ts[k].cpu().numpy(), Qs[k].cpu().numpy(), ws[k].cpu().numpy(), 0, f"rep{rep} m{k}")
 
+
+
+def test_batched_orders_above_320_on_half_grid(gpu):
+    """Orders above 320 are taken by the lower half of the global grid first;
+    the rest of the global tier and the LDS tier follow (all against the
+    oracle)."""
+    import torch
+    import paper_2007_03576_amd as hq
+    sizes = [400, 340, 330, 321, 320, 200, 97, 96, 50, 5]
+    _say(f"case batched orders {sizes}")
+    mats = [hi.gaussian_hessenberg(n, seed=900 + i) for i, n in enumerate(sizes)]
+    Ts, Qs, ws, info = hq.schur_batched([torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in mats])
+    torch.cuda.synchronize()
+    info = info.cpu().numpy()
+    for i, H in enumerate(mats):
+        check_one(H, Ts[i].cpu().numpy(), Qs[i].cpu().numpy(), ws[i].cpu().numpy(), int(info[i]), f"w{i} n={H.shape[0]}")
