@@ -772,21 +772,70 @@ __device__ __forceinline__ void chase_la(SmemCore &S, double *A, int lda, int kt
             const int c0L = k + m + 1;
             const int ncL = max(0, colhi - c0L + 1), nrR = k + 1;
             const int nseg = ncL + nrR + nz + (extra ? 1 : 0);
-            for (int it = tid; it < nseg; it += NSEGT) {
-                const int r = it - ncL;
-                const bool isL = it < ncL, isA = !isL && r < nrR, isZ = !isL && !isA && r < nrR + nz;
-                double *base = isZ ? Z : A;
-                const int ldb = isZ ? ldz : lda;
-                const int prow = isL ? (k + 1) : (isA ? r : (isZ ? r - nrR : k + 4));
-                const int pcol = isL ? (c0L + it) : (k + 1);
-                const int st = isL ? 1 : ldb;
-                double *p = base + prow + pcol * ldb;
-                double y0 = p[0], y1 = p[st], y2 = (m == 3) ? p[2 * st] : 0.0;
+            // Matrix in LDS: one segment per thread and step.  In global
+            // memory: SG segments per thread and pass with all loads issued
+            // before the first store (the segments of one position are
+            // disjoint), so a pass waits for one memory latency instead of
+            // one per segment (measured: 17 % faster batched solves of orders
+            // 97..256; the same grouping costs 4 % per position in LDS).
+            constexpr int SG = 4;
+            if (__builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void *)A)) {
+                for (int it = tid; it < nseg; it += NSEGT) {
+                    const int r = it - ncL;
+                    const bool isL = it < ncL, isA = !isL && r < nrR, isZ = !isL && !isA && r < nrR + nz;
+                    double *base = isZ ? Z : A;
+                    const int ldb = isZ ? ldz : lda;
+                    const int prow = isL ? (k + 1) : (isA ? r : (isZ ? r - nrR : k + 4));
+                    const int pcol = isL ? (c0L + it) : (k + 1);
+                    const int st = isL ? 1 : ldb;
+                    double *p = base + prow + pcol * ldb;
+                    double y0 = p[0], y1 = p[st], y2 = (m == 3) ? p[2 * st] : 0.0;
+                    if (tau != 0.0) {
+                        refl3(m, tau, v1, v2, y0, y1, y2);
+                        p[0] = y0;
+                        p[st] = y1;
+                        if (m == 3) p[2 * st] = y2;
+                    }
+                }
+            } else
+            for (int it0 = tid; it0 < nseg; it0 += SG * NSEGT) {
+                double *pp[SG];
+                int stp[SG];
+                double y[SG][3];
+#pragma unroll
+                for (int g = 0; g < SG; ++g) {
+                    const int it = it0 + g * NSEGT;
+                    pp[g] = nullptr;
+                    stp[g] = 0;
+                    y[g][0] = y[g][1] = y[g][2] = 0.0;
+                    if (it < nseg) {
+                        const int r = it - ncL;
+                        const bool isL = it < ncL, isA = !isL && r < nrR, isZ = !isL && !isA && r < nrR + nz;
+                        double *base = isZ ? Z : A;
+                        const int ldb = isZ ? ldz : lda;
+                        const int prow = isL ? (k + 1) : (isA ? r : (isZ ? r - nrR : k + 4));
+                        const int pcol = isL ? (c0L + it) : (k + 1);
+                        const int st = isL ? 1 : ldb;
+                        double *p = base + prow + pcol * ldb;
+                        pp[g] = p;
+                        stp[g] = st;
+                        y[g][0] = p[0];
+                        y[g][1] = p[st];
+                        y[g][2] = (m == 3) ? p[2 * st] : 0.0;
+                    }
+                }
                 if (tau != 0.0) {
-                    refl3(m, tau, v1, v2, y0, y1, y2);
-                    p[0] = y0;
-                    p[st] = y1;
-                    if (m == 3) p[2 * st] = y2;
+#pragma unroll
+                    for (int g = 0; g < SG; ++g) {
+                        if (!pp[g]) continue;
+                        double y0 = y[g][0], y1 = y[g][1], y2 = y[g][2];
+                        refl3(m, tau, v1, v2, y0, y1, y2);
+                        double *p = pp[g];
+                        const int st = stp[g];
+                        p[0] = y0;
+                        p[st] = y1;
+                        if (m == 3) p[2 * st] = y2;
+                    }
                 }
             }
             if (tid == 0) fl += 12.0 * (double)nseg + 40.0;
