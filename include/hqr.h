@@ -89,7 +89,8 @@ int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double
  * in global memory (the L2-resident path).  A counting sort on the device
  * orders the batch by decreasing order; two persistent grids (global tier,
  * then LDS tier) take matrices from that queue one at a time, longest first;
- * orders above 320 go to half of the global grid only (cache footprint).
+ * orders above a threshold go to half of the global grid only (cache
+ * footprint; see hqr_set_batched_launch).
  * Every order runs double-shift steps (hqr_params.small_shifts does not
  * apply here).  Matrices of order 0 get info 0 and are not touched.
  * Eigenvalues of matrix i go to wr/wi + eig_offsets[i]; info[i] receives the
@@ -102,6 +103,17 @@ int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double
  * use different queues.  Returns 0, or -k for a bad argument k. */
 int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int32_t batch,
                       double *wr, double *wi, const int64_t *eig_offsets, int32_t *info, void *stream);
+
+/* Launch shape of the batched form's global-memory grid (orders > 96):
+ * wg_per_cu workgroups per CU (1..8, default 2), and orders above wide_n
+ * (96..4095, default 320) taken by half of that grid only, so that the
+ * cache footprint of the matrices in flight (about 176*n bytes per bulge
+ * position each) stays within L2.  Chosen by timing (the package's
+ * autotuner); applies to later hqr_schur_batched calls.  Returns 0, -1 bad
+ * wg_per_cu, -2 bad wide_n. */
+int hqr_set_batched_launch(int32_t wg_per_cu, int32_t wide_n);
+/* Current values (host pointers); returns 0, or -1 for a NULL pointer. */
+int hqr_get_batched_launch(int32_t *wg_per_cu, int32_t *wide_n);
 
 /* Backward pass of the eigenvalues for a batch of Schur forms (T_i, Q_i) of
  * equal order n stored back to back, column major (T + i*n*n).  Given the cotangents

@@ -9,7 +9,8 @@ import torch
 from ._lib import HqrError, HqrParams, check, lib
 
 __all__ = ["schur", "schur_colmajor", "schur_batched", "eigvals", "set_params", "params",
-           "last_stats", "HqrError", "BatchedProblem", "BatchedGraph"]
+           "last_stats", "HqrError", "BatchedProblem", "BatchedGraph", "set_batched_launch",
+           "batched_launch"]
 
 
 def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
@@ -96,6 +97,17 @@ def schur(H: torch.Tensor, want_q: bool = True, Q0: Optional[torch.Tensor] = Non
     info = schur_colmajor(Hf, Qf, wr, wi, params=params, stream=stream)
     w = torch.complex(wr[:n], wi[:n])
     return Hf, Qf, w, info
+
+
+def set_batched_launch(wg_per_cu: int, wide_n: int) -> None:
+    """Launch shape of the batched global-memory grid (hqr_set_batched_launch)."""
+    check(lib().hqr_set_batched_launch(int(wg_per_cu), int(wide_n)), "hqr_set_batched_launch")
+
+
+def batched_launch() -> dict:
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    check(lib().hqr_get_batched_launch(ctypes.byref(a), ctypes.byref(b)), "hqr_get_batched_launch")
+    return {"wg_per_cu": a.value, "wide_n": b.value}
 
 
 class BatchedProblem:

@@ -1,0 +1,68 @@
+"""Launch-shape autotuner of the batched form.
+
+The batched form's global-memory grid (orders above 96, one workgroup per
+matrix, H and Q in global memory) is bound by the memory round trips of the
+double-shift chase and by the cache footprint of the matrices in flight:
+more workgroups per CU hide more latency until their rows and columns no
+longer fit the CU's share of L2, and large orders are better run with half
+the grid.  The tuner times each (workgroups per CU, order above which half
+the grid is used) candidate on a seeded sample drawn like the workload
+(Gaussian Hessenberg matrices with orders uniform in [lo, hi]) and installs
+the fastest whose solves all succeeded.  The paper calibrates StarPU
+performance models instead (Sec. 3); this table plays that role for the
+batched form.
+"""
+from __future__ import annotations
+
+import time
+from typing import Dict, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import api
+
+CANDIDATES: Tuple[Tuple[int, int], ...] = ((1, 4095), (2, 320), (2, 4095), (3, 320), (2, 200))
+
+
+def sample(lo: int, hi: int, count: int, seed: int, device) -> tuple:
+    """Seeded Gaussian Hessenberg matrices (N(0,1) on and above the first
+    subdiagonal) with orders uniform in [lo, hi], packed column major."""
+    sizes = np.random.default_rng(seed).integers(lo, hi + 1, size=count)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    mats = [torch.randn(int(n), int(n), generator=g, dtype=torch.float64, device=device).triu(-1)
+            for n in sizes]
+    return [int(s) for s in sizes], api.pack(mats)
+
+
+def tune(lo: int, hi: int, count: int = 0, seed: int = 7, device="cuda",
+         candidates: Sequence[Tuple[int, int]] = CANDIDATES, reps: int = 1, apply: bool = True) -> Dict:
+    """Times hqr_schur_batched on `count` sampled matrices (default: four per
+    CU) for each (wg_per_cu, wide_n) candidate; returns {"wg_per_cu",
+    "wide_n", "seconds": {candidate: s}} and installs the best if apply."""
+    dev = torch.device(device)
+    if count <= 0:
+        count = 4 * torch.cuda.get_device_properties(dev).multi_processor_count
+    sizes, packed = sample(lo, hi, count, seed, dev)
+    prob = api.BatchedProblem(sizes, True, dev)
+    prev = api.batched_launch()
+    times = {}
+    try:
+        for wg, wide in candidates:
+            api.set_batched_launch(wg, wide)
+            best = float("inf")
+            for _ in range(reps):
+                prob.load(packed)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                prob.solve()
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            times[(wg, wide)] = best if int(prob.info.abs().max()) == 0 else float("inf")
+    finally:
+        api.set_batched_launch(prev["wg_per_cu"], prev["wide_n"])
+    wg, wide = min(times, key=times.get)
+    if apply:
+        api.set_batched_launch(wg, wide)
+    return {"wg_per_cu": wg, "wide_n": wide, "seconds": {f"{a},{b}": t for (a, b), t in times.items()}}

@@ -121,7 +121,7 @@ hipError_t launch_transpose_pad(const double *V, int64_t ldv, int K, double *Ut,
 constexpr int QHDR = 8;
 hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch,
                           double *wr, double *wi, const int64_t *eoff, int32_t *info, int32_t *queue,
-                          hipStream_t s);
+                          int wg_per_cu, int wide_n, hipStream_t s);
 hipError_t launch_eig_backward(const double *T, const double *Q, int n, int batch, const double *wr,
                                const double *wi, const double *gwr, const double *gwi, double *dH,
                                int hess_mask, hipStream_t s);

@@ -42,6 +42,13 @@ struct QueueBuf {
     int64_t cap = 0;
 };
 std::map<std::pair<int, void *>, QueueBuf> g_queues;
+
+// Launch shape of the batched global-memory grid: workgroups per CU, and the
+// order above which matrices go to half of that grid only.  Per bulge
+// position a workgroup touches about 176*n bytes of H and Q (n cache lines
+// for three rows, three columns of H and Q); two workgroups per CU keep that
+// inside the CU's share of L2 (4 MB per 32 CUs) up to about n = 360.
+int g_batched_wg_per_cu = 2, g_batched_wide_n = 320;
 thread_local int64_t t_stats[8];
 
 struct Params {
@@ -1076,8 +1083,11 @@ int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_
     if (!eig_offsets) return -8;
     if (!info) return -9;
     int32_t *queue = nullptr;
+    int wg_per_cu, wide_n;
     {
         std::lock_guard<std::mutex> lk(g_mu);
+        wg_per_cu = g_batched_wg_per_cu;
+        wide_n = g_batched_wide_n;
         int dev = 0;
         CK(hipGetDevice(&dev));
         QueueBuf &qb = g_queues[std::make_pair(dev, stream)];
@@ -1094,7 +1104,27 @@ int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_
         }
         queue = qb.p;
     }
-    CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, queue, (hipStream_t)stream));
+    CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, queue, wg_per_cu, wide_n,
+                      (hipStream_t)stream));
+    return 0;
+}
+
+int hqr_set_batched_launch(int32_t wg_per_cu, int32_t wide_n)
+{
+    if (wg_per_cu < 1 || wg_per_cu > 8) return -1;
+    if (wide_n < MMAX || wide_n > 4095) return -2;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_batched_wg_per_cu = wg_per_cu;
+    g_batched_wide_n = wide_n;
+    return 0;
+}
+
+int hqr_get_batched_launch(int32_t *wg_per_cu, int32_t *wide_n)
+{
+    if (!wg_per_cu || !wide_n) return -1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    *wg_per_cu = g_batched_wg_per_cu;
+    *wide_n = g_batched_wide_n;
     return 0;
 }
 

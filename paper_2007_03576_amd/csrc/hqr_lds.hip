@@ -2508,25 +2508,19 @@ __device__ __forceinline__ int queue_next(SmemCore &S, int32_t *head)
     return k;
 }
 
-// Orders above WIDE_N go only to the lower half of the global-memory grid
-// (about one workgroup per CU).  Per bulge position a workgroup touches
-// about 176*n bytes of H and Q (n cache lines for three rows, three columns
-// of H and Q); two workgroups per CU keep that inside the CU's share of L2
-// (4 MB per 32 CUs) up to about n = 360, and one does up to about 700.
-constexpr int WIDE_N = 320;
-
 constexpr int QBINS = 4096;
 constexpr int QNT = 1024;
 __device__ __forceinline__ int order_bin(int n) { return n <= 0 ? 0 : min(n, QBINS - 1); }
 
 // Longest-first order of the batch: counting sort of the orders (one
 // workgroup, bins in LDS), then the queue heads: q[0] = 0 for the orders
-// above WIDE_N (positions [0, q[5])), q[4] = q[5] for the other orders of
+// above wide_n (positions [0, q[5])), q[4] = q[5] for the other orders of
 // the global tier (positions [q[5], q[2])), q[1] = q[2] = number of orders
 // above the LDS limit for the LDS tier (positions [q[2], q[3])), q[3] =
 // number of positive orders.  Empty matrices (order <= 0, sorted last) are
 // finished here.
-__global__ void __launch_bounds__(QNT) k_batched_order(const int32_t *nn, int batch, int32_t *q, int32_t *info)
+__global__ void __launch_bounds__(QNT) k_batched_order(const int32_t *nn, int batch, int wide_n, int32_t *q,
+                                                       int32_t *info)
 {
     __shared__ int cnt[QBINS];
     __shared__ int part[QNT];
@@ -2555,7 +2549,7 @@ __global__ void __launch_bounds__(QNT) k_batched_order(const int32_t *nn, int ba
     }
     __syncthreads();
     const int nbig = cnt[MMAX];   // start of bin MMAX = number of orders above MMAX
-    const int nwide = cnt[WIDE_N]; // number of orders above WIDE_N
+    const int nwide = cnt[wide_n]; // number of orders above wide_n (MMAX <= wide_n < QBINS)
     const int npos = cnt[0];      // start of bin 0 = number of positive orders
     __syncthreads();
     int32_t *order = q + QHDR;
@@ -2639,7 +2633,7 @@ __global__ void __launch_bounds__(NT) k_batched_global(double *H, double *Q, con
     const int tid = threadIdx.x;
     const int32_t *order = q + QHDR;
     const int nbig = q[2], nwide = q[5];
-    // the lower half of the grid takes the orders above WIDE_N first, then
+    // the lower half of the grid takes the orders above wide_n first, then
     // joins the upper half on the rest
     bool wide = blockIdx.x < (gridDim.x + 1) / 2 && nwide > 0;
     for (;;) {
@@ -2675,7 +2669,8 @@ __global__ void __launch_bounds__(NT) k_batched_global(double *H, double *Q, con
 }
 
 hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch, double *wr,
-                          double *wi, const int64_t *eoff, int32_t *info, int32_t *queue, hipStream_t s)
+                          double *wi, const int64_t *eoff, int32_t *info, int32_t *queue, int wg_per_cu, int wide_n,
+                          hipStream_t s)
 {
     hipError_t e = prep((const void *)k_batched);
     if (e != hipSuccess) return e;
@@ -2683,10 +2678,13 @@ hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const in
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     ncu = std::max(ncu, 1);
-    hipLaunchKernelGGL(k_batched_order, dim3(1), dim3(QNT), 0, s, n, batch, queue, info);
+    wide_n = std::min(std::max(wide_n, MMAX), QBINS - 1);
+    wg_per_cu = std::min(std::max(wg_per_cu, 1), 8);
+    hipLaunchKernelGGL(k_batched_order, dim3(1), dim3(QNT), 0, s, n, batch, wide_n, queue, info);
     // orders > MMAX first (they dominate the time), then the LDS tier; each
     // grid drains its queue longest-first
-    hipLaunchKernelGGL(k_batched_global, dim3(std::min(batch, 2 * ncu)), dim3(NT), 0, s, H, Q, offsets, n, batch,
+    hipLaunchKernelGGL(k_batched_global, dim3(std::min(batch, wg_per_cu * ncu)), dim3(NT), 0, s, H, Q, offsets, n,
+                       batch,
                        wr, wi, eoff, info, queue);
     hipLaunchKernelGGL(k_batched, dim3(std::min(batch, ncu)), dim3(NT), smem_bytes(), s, H, Q, offsets, n, batch,
                        wr, wi, eoff, info, queue);

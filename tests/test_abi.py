@@ -61,3 +61,19 @@ def test_params_roundtrip_and_rejection(L):
     assert L.hqr_set_params(ctypes.byref(old)) == 0
     assert L.hqr_set_params(None) == -1
 
+
+
+def test_batched_launch_roundtrip_and_rejection(L):
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    assert L.hqr_get_batched_launch(ctypes.byref(a), ctypes.byref(b)) == 0
+    old = (a.value, b.value)
+    assert old == (2, 320)
+    assert L.hqr_set_batched_launch(3, 400) == 0
+    assert L.hqr_get_batched_launch(ctypes.byref(a), ctypes.byref(b)) == 0
+    assert (a.value, b.value) == (3, 400)
+    assert L.hqr_set_batched_launch(0, 400) == -1
+    assert L.hqr_set_batched_launch(9, 400) == -1
+    assert L.hqr_set_batched_launch(2, 95) == -2
+    assert L.hqr_set_batched_launch(2, 4096) == -2
+    assert L.hqr_get_batched_launch(None, ctypes.byref(b)) == -1
+    assert L.hqr_set_batched_launch(*old) == 0

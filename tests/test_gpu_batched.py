@@ -173,3 +173,32 @@ def test_batched_orders_above_320_on_half_grid(gpu):
     info = info.cpu().numpy()
     for i, H in enumerate(mats):
         check_one(H, Ts[i].cpu().numpy(), Qs[i].cpu().numpy(), ws[i].cpu().numpy(), int(info[i]), f"w{i} n={H.shape[0]}")
+
+
+def test_autotune_launch_shape_installed_and_results_unchanged(gpu):
+    """The launch-shape tuner installs one of its candidates; the solve under
+    the tuned shape is bit-identical to the default shape (one workgroup per
+    matrix either way, only the grid and queue split change)."""
+    import torch
+    import paper_2007_03576_amd as hq
+    from paper_2007_03576_amd import autotune
+    _say("case autotune launch shape orders 97..360 count 64")
+    prev = hq.batched_launch()
+    try:
+        tab = autotune.tune(97, 360, count=64, seed=5)
+        assert (tab["wg_per_cu"], tab["wide_n"]) in autotune.CANDIDATES
+        assert hq.batched_launch() == {"wg_per_cu": tab["wg_per_cu"], "wide_n": tab["wide_n"]}
+        sizes, packed = autotune.sample(90, 400, 12, 6, "cuda")
+        outs = []
+        for wg, wide in [(2, 320), (1, 4095), (3, 200)]:
+            hq.set_batched_launch(wg, wide)
+            p = hq.BatchedProblem(sizes)
+            p.load(packed)
+            p.solve()
+            torch.cuda.synchronize()
+            assert int(p.info.abs().max()) == 0
+            outs.append((p.H.clone(), p.Q.clone()))
+        for H, Q in outs[1:]:
+            assert torch.equal(H, outs[0][0]) and torch.equal(Q, outs[0][1])
+    finally:
+        hq.set_batched_launch(prev["wg_per_cu"], prev["wide_n"])
