@@ -137,7 +137,9 @@ def grad_run(seed):
     import paper_2007_03576_amd as hq
     from paper_2007_03576_amd import autotune
     H, _ = hi.prescribed_batch_device(512, 512, seed=seed, device="cuda")
-    shape = autotune.tune(512, 512, count=512, seed=seed + 3)  # launch shape for 512 matrices of order 512
+    # launch shape for 512 matrices of order 512 (candidates that differ at this order)
+    shape = autotune.tune(512, 512, count=512, seed=seed + 3,
+                          candidates=((1, 4095), (2, 4095), (2, 320), (3, 320), (4, 320)))
     fw = bw = None
     for _ in range(2):
         X = H.clone().requires_grad_(True)

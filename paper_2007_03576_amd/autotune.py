@@ -22,7 +22,8 @@ import torch
 
 from . import api
 
-CANDIDATES: Tuple[Tuple[int, int], ...] = ((1, 4095), (2, 320), (2, 4095), (3, 320), (2, 200))
+CANDIDATES: Tuple[Tuple[int, int], ...] = ((1, 4095), (2, 4095), (2, 320), (2, 200), (2, 160), (2, 128),
+                                           (3, 320), (3, 200), (4, 160))
 
 
 def sample(lo: int, hi: int, count: int, seed: int, device) -> tuple:
