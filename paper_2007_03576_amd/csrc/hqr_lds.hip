@@ -778,7 +778,7 @@ __device__ __forceinline__ void chase_la(SmemCore &S, double *A, int lda, int kt
             // disjoint), so a pass waits for one memory latency instead of
             // one per segment (measured: 17 % faster batched solves of orders
             // 97..256; the same grouping costs 4 % per position in LDS).
-            constexpr int SG = 4;
+            constexpr int SG = 8;
             if (__builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void *)A)) {
                 for (int it = tid; it < nseg; it += NSEGT) {
                     const int r = it - ncL;
