@@ -25,6 +25,13 @@ def lib():
         i64 = ctypes.c_int64
         L.hqr_oracle_schur_ex.argtypes = [dp, dp, i64, i64, dp, dp, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_int, i64, ctypes.POINTER(ctypes.c_int64)]
+        L.hqr_oracle_schur_defl.argtypes = [dp, dp, i64, i64, dp, dp, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, i64, ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.c_int, ctypes.c_double]
+        L.hqr_oracle_aed_ex.argtypes = [dp, dp, i64, i64, i64, i64, ctypes.c_int, dp, dp,
+                                        ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double]
+        L.hqr_oracle_swap_rejections.argtypes = [ctypes.c_int]
+        L.hqr_oracle_swap_rejections.restype = ctypes.c_int64
         L.hqr_oracle_sweep.argtypes = [dp, dp, i64, i64, i64, i64, ctypes.c_int, dp, dp, ctypes.c_int]
         L.hqr_oracle_swap.argtypes = [dp, dp, i64, i64, i64, ctypes.c_int, ctypes.c_int]
         L.hqr_oracle_std2x2.argtypes = [dp] * 6
@@ -57,8 +64,14 @@ def force_swap_failure(on: bool) -> None:
     lib().hqr_oracle_force_swap_failure(1 if on else 0)
 
 
-def schur(H, want_q=True, Q0=None, ns=0, nw=0, nmin=0, itmax=0):
-    """Returns (T, Q, w, info, stats); w is complex in diagonal order."""
+def swap_rejections(reset=False) -> int:
+    """Swaps rejected by the stability test since the last reset."""
+    return int(lib().hqr_oracle_swap_rejections(1 if reset else 0))
+
+
+def schur(H, want_q=True, Q0=None, ns=0, nw=0, nmin=0, itmax=0, defl_mode=0, defl_thold=0.0):
+    """Returns (T, Q, w, info, stats); w is complex in diagonal order.
+    defl_mode: 0 LAPACK-style, 1 norm-stable, 2 fixed (threshold defl_thold)."""
     T = _fortran(H)
     n = T.shape[0]
     Q = None
@@ -67,8 +80,8 @@ def schur(H, want_q=True, Q0=None, ns=0, nw=0, nmin=0, itmax=0):
     wr = np.zeros(max(n, 1))
     wi = np.zeros(max(n, 1))
     st = (ctypes.c_int64 * 6)()
-    info = lib().hqr_oracle_schur_ex(_p(T), _p(Q), n, max(n, 1), _p(wr), _p(wi), ns, nw, nmin,
-                                     itmax, st)
+    info = lib().hqr_oracle_schur_defl(_p(T), _p(Q), n, max(n, 1), _p(wr), _p(wi), ns, nw, nmin,
+                                       itmax, st, int(defl_mode), float(defl_thold))
     return T, Q, (wr + 1j * wi)[:n], info, list(st)
 
 
@@ -102,14 +115,17 @@ def std2x2(B):
     return Bn, cs.value, sn.value, cplx
 
 
-def aed(H, Q, ktop, kbot, nw):
+def aed(H, Q, ktop, kbot, nw, defl_mode=0, defl_thold=0.0):
     T = _fortran(H)
     n = T.shape[0]
     Qo = _fortran(Q) if Q is not None else None
     cr = np.zeros(n + 1)
     ci = np.zeros(n + 1)
     nc = ctypes.c_int(0)
-    nd = lib().hqr_oracle_aed(_p(T), _p(Qo), n, n, ktop, kbot, nw, _p(cr), _p(ci), ctypes.byref(nc))
+    nd = lib().hqr_oracle_aed_ex(_p(T), _p(Qo), n, n, ktop, kbot, nw, _p(cr), _p(ci), ctypes.byref(nc),
+                                 int(defl_mode), float(defl_thold))
+    if nd < 0:
+        raise ValueError(f"hqr_oracle_aed_ex returned {nd}")
     return T, Qo, nd, (cr + 1j * ci)[: nc.value]
 
 

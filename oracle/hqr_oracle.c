@@ -13,10 +13,12 @@
  *   - the sweep introduces a tightly coupled chain of bulges one by one and
  *     chases them as a unit (Sec. 2.3, Fig. multi_shift);
  *   - AED follows the three sub-steps of Sec. 2.5 (Fig. multi_shift_aed):
- *     Schur-reduce the window, test candidates bottom-up with the LAPACK-style
- *     conditions of Sec. 5.3 (item 1) and move failures to the top with
- *     Bai-Demmel swaps, then remove the spike by a Householder reflector and a
- *     Householder Hessenberg reduction;
+ *     Schur-reduce the window, test candidates bottom-up with the deflation
+ *     conditions of Sec. 5.6 "Comment regarding the deflation conditions and
+ *     the accuracy" (LAPACK-style by default; norm-stable and fixed on
+ *     request) and move failures to the top with Bai-Demmel swaps, then
+ *     remove the spike by a Householder reflector and a Householder
+ *     Hessenberg reduction;
  *   - failed candidates become the next shifts; the AED step is repeated when
  *     it deflated many eigenvalues (Sec. 2.5, last paragraph).
  * Readings of points the paper leaves open are marked "Reading:".
@@ -49,12 +51,31 @@ void hqr_oracle_force_swap_failure(int on) { g_force_reject = on; }
  *  6  AED deflation threshold loosened by 1e8
  *  7  gradient uses g instead of conj(g)
  *  8  spike reflector is not applied to the columns right of the undeflated part
+ *  9  the 2x2 AED threshold h^ drops both square roots
+ * 10  the 2x2 AED threshold h^ uses |t(k-1,k)| in place of sqrt|t(k-1,k) t(k,k-1)|
+ * 11  the swap acceptance threshold drops the factor ||D||_max (10 u only)
+ * 12  the norm-stable / fixed 2x2 AED test looks at the bottom spike entry only
+ * 13  the norm-stable threshold uses max |h_ij| in place of ||H||_F
  */
+
+/* Swaps rejected by the stability test since the last reset (test hook). */
+static long g_rejects = 0;
+int64_t hqr_oracle_swap_rejections(int reset)
+{
+    long r = g_rejects;
+    if (reset) g_rejects = 0;
+    return (int64_t)r;
+}
 
 typedef struct {
     int ns, nw, nmin, nibble, kexsh;
     long itmax;
     double smlnum; /* nu * n / u with n the order of the full problem */
+    /* Deflation conditions (Sec. 5.6): 0 = LAPACK-style; 1 = norm-stable and
+       2 = fixed, both an absolute threshold dthr on subdiagonal and spike
+       entries (u ||H||_F resp. the caller's epsilon_thold). */
+    int defl_mode;
+    double dthr;
     int64_t *stats;
 } oparams;
 
@@ -326,12 +347,17 @@ static void eig2(double a, double b, double c, double d, double *r1, double *i1,
 /* ------------------------------------------------------------------------- */
 
 /* Vigilant test of the subdiagonal entry H[k,k-1] inside the block [lo,hi].
-   Reading: the LAPACK-style vigilant check is the Ahues-Tisseur criterion
-   (LAWN 122): first |h21| <= u(|h11|+|h22|) (neighbours if that sum is 0),
-   then |h21||h12| <= u |h22| |h11-h22| in an overflow-safe form, floor smlnum. */
-static int negligible(const double *H, long ld, int k, int lo, int hi, double smlnum)
+   LAPACK-style (Sec. 5.6, item 1; reading): the paper only says the vigilant
+   check mirrors LAPACK 3.9.0, whose documented test is the Ahues-Tisseur
+   criterion (LAWN 122): first |h21| <= u(|h11|+|h22|) (neighbours if that
+   sum is 0), then |h21||h12| <= u |h22| |h11-h22| in an overflow-safe form,
+   floor smlnum.  Norm-stable and fixed conditions (items 2 and 3): the entry
+   itself against the absolute threshold. */
+static int negligible(const double *H, long ld, int k, int lo, int hi, const oparams *P)
 {
     double h21 = fabs(H[IX(k, k - 1, ld)]);
+    if (P->defl_mode != 0) return h21 <= P->dthr;
+    double smlnum = P->smlnum;
     if (h21 <= smlnum) return 1;
     double h11 = H[IX(k - 1, k - 1, ld)], h22 = H[IX(k, k, ld)];
     double tst = fabs(h11) + fabs(h22);
@@ -373,9 +399,14 @@ static void shift_column(const double *H, long ld, int ktop, int kbot, double re
 /* Chase nb = nshifts/2 bulges through [ktop,kbot] of the n x n matrix H.
    Bulge j enters at step 3j (when bulge j-1 has moved three rows) and every
    step moves each bulge one row, the lowest bulge first.  Each reflector is
-   applied at once to the full rows and columns of H and to Q. */
+   applied at once to the full rows and columns of H and to Q.
+   Vigilant deflation (Sec. 3.2, 'push bulges': the tasks of the last set of
+   tightly coupled bulges scan the subdiagonal): a subdiagonal entry is tested
+   right after the topmost bulge -- the last one of the chain -- has passed
+   it, when no later reflector of the sweep reads or changes it; this equals
+   one scan after the sweep. */
 static long sweep(double *H, long ld, int n, double *Q, long ldq, int nq, int ktop, int kbot,
-                  int nshifts, const double *sr, const double *si, int vigilant, double smlnum)
+                  int nshifts, const double *sr, const double *si, int vigilant, const oparams *P)
 {
     int nb = nshifts / 2;
     long nrefl = 0;
@@ -406,8 +437,8 @@ static long sweep(double *H, long ld, int n, double *Q, long ldq, int nq, int kt
             refl_right(H, ld, k + 1, m, v, tau, 0, r1);
             if (g_mut != 2) refl_right(Q, ldq, k + 1, m, v, tau, 0, nq - 1);
             ++nrefl;
-            if (vigilant && k >= ktop && H[IX(k + 1, k, ld)] != 0.0 &&
-                negligible(H, ld, k + 1, ktop, kbot, smlnum))
+            if (vigilant && j == nb - 1 && k >= ktop && H[IX(k + 1, k, ld)] != 0.0 &&
+                negligible(H, ld, k + 1, ktop, kbot, P))
                 H[IX(k + 1, k, ld)] = 0.0;
         }
     }
@@ -421,8 +452,10 @@ int hqr_oracle_sweep(double *H, double *Q, int64_t n, int64_t ld, int64_t ktop, 
     if (ld < (n > 1 ? n : 1)) return -4;
     if (ktop < 0 || kbot >= n || ktop > kbot) return -5;
     if (nshifts < 0 || (nshifts & 1)) return -7;
-    double smlnum = DBL_MIN * ((double)n / U);
-    sweep(H, ld, (int)n, Q, ld, (int)n, (int)ktop, (int)kbot, nshifts, sr, si, vigilant, smlnum);
+    oparams P;
+    memset(&P, 0, sizeof P);
+    P.smlnum = DBL_MIN * ((double)n / U);
+    sweep(H, ld, (int)n, Q, ld, (int)n, (int)ktop, (int)kbot, nshifts, sr, si, vigilant, &P);
     return 0;
 }
 
@@ -445,7 +478,7 @@ static int qr_small(double *H, long ld, int n, double *Q, long ldq, int nq, int 
         for (;;) {
             for (l = i; l > ilo; --l) {
                 if (H[IX(l, l - 1, ld)] == 0.0) break;
-                if (negligible(H, ld, l, ilo, i, P->smlnum)) {
+                if (negligible(H, ld, l, ilo, i, P)) {
                     H[IX(l, l - 1, ld)] = 0.0;
                     break;
                 }
@@ -478,7 +511,7 @@ static int qr_small(double *H, long ld, int n, double *Q, long ldq, int nq, int 
                 double pick = (fabs(sr[0] - hii) <= fabs(sr[1] - hii)) ? sr[0] : sr[1];
                 sr[0] = sr[1] = pick;
             }
-            long nr = sweep(H, ld, n, Q, ldq, nq, l, i, 2, sr, si, 0, P->smlnum);
+            long nr = sweep(H, ld, n, Q, ldq, nq, l, i, 2, sr, si, 0, P);
             if (P->stats) P->stats[5] += nr;
             ++its;
             ++total;
@@ -575,7 +608,7 @@ static int swap_blocks(double *T, long ld, int nt, double *V, long ldv, int nv, 
             D[r + 4 * c] = T[IX(j + r, j + c, ld)];
             dnorm = dmax(dnorm, fabs(D[r + 4 * c]));
         }
-    double thresh = dmax(10.0 * U * dnorm, smlnum);
+    double thresh = dmax(10.0 * U * ((g_mut == 11) ? 1.0 : dnorm), smlnum);
     /* Sylvester equation A11 X - X A22 = A12 (p x q) through its Kronecker form */
     int pq = p * q;
     double K[16] = {0}, rhs[4], X[4];
@@ -639,7 +672,10 @@ static int swap_blocks(double *T, long ld, int nt, double *V, long ldv, int nv, 
                 for (int l2 = 0; l2 < m; ++l2) s += Qs[r + 4 * l] * Dn[l + 4 * l2] * Qs[c + 4 * l2];
             err2 = dmax(err2, fabs(s - D[r + 4 * c]));
         }
-    if (err1 > thresh || err2 > thresh) return 1;
+    if (err1 > thresh || err2 > thresh) {
+        ++g_rejects;
+        return 1;
+    }
     double G[16];
     for (int c = 0; c < m; ++c)
         for (int r = 0; r < m; ++r) G[r + m * c] = Qs[r + 4 * c];
@@ -766,12 +802,22 @@ static int aed_step(double *H, long ld, int n, double *Q, long ldq, int nq, int 
         if (two && ns - 2 < ilst) break; /* a 2x2 block straddling the boundary */
         int k = ns - 1;
         int defl;
-        if (!two) {
+        if (P->defl_mode != 0) {
+            /* norm-stable / fixed conditions: every spike entry of the block
+               against the absolute threshold */
+            defl = fabs(V[IX(nw, k, ldv)]) <= P->dthr;
+            if (two && g_mut != 12) defl = defl && fabs(V[IX(nw, k - 1, ldv)]) <= P->dthr;
+        } else if (!two) {
             double foo = fabs(T[IX(k, k, ldt)]);
             defl = fabs(V[IX(nw, k, ldv)]) <= dmax(P->smlnum, thr_scale * U * foo);
         } else {
-            double hh = sqrt(fabs(T[IX(k, k, ldt)] * T[IX(k - 1, k - 1, ldt)])) +
-                        sqrt(fabs(T[IX(k - 1, k, ldt)] * T[IX(k, k - 1, ldt)]));
+            /* h^ of the 2x2 block as printed in Sec. 5.6, item 1 */
+            double d1 = fabs(T[IX(k, k, ldt)] * T[IX(k - 1, k - 1, ldt)]);
+            double d2 = fabs(T[IX(k - 1, k, ldt)] * T[IX(k, k - 1, ldt)]);
+            double hh;
+            if (g_mut == 9) hh = d1 + d2;
+            else if (g_mut == 10) hh = sqrt(d1) + fabs(T[IX(k - 1, k, ldt)]);
+            else hh = sqrt(d1) + sqrt(d2);
             double sp = dmax(fabs(V[IX(nw, k, ldv)]), fabs(V[IX(nw, k - 1, ldv)]));
             defl = sp <= dmax(P->smlnum, thr_scale * U * hh);
         }
@@ -863,8 +909,44 @@ static int aed_step(double *H, long ld, int n, double *Q, long ldq, int nq, int 
     return nd;
 }
 
-int hqr_oracle_aed(double *H, double *Q, int64_t n, int64_t ld, int64_t ktop, int64_t kbot,
-                   int nw, double *cr, double *ci, int *ncand)
+/* Frobenius norm of the Hessenberg part of H (overflow-safe), for the
+   norm-stable deflation conditions. */
+static double hess_fro(const double *H, long ld, int n)
+{
+    double scale = 0, ssq = 1, amax = 0;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n && i <= j + 1; ++i) {
+            double a = fabs(H[IX(i, j, ld)]);
+            if (a == 0) continue;
+            amax = dmax(amax, a);
+            if (a > scale) {
+                ssq = 1 + ssq * (scale / a) * (scale / a);
+                scale = a;
+            } else {
+                ssq += (a / scale) * (a / scale);
+            }
+        }
+    return (g_mut == 13) ? amax : scale * sqrt(ssq);
+}
+
+/* Deflation threshold of the conditions of Sec. 5.6: mode 1 (norm-stable)
+   u ||H||_F of the whole input, computed once (an orthogonal similarity keeps
+   the norm, and the recursive window solve inherits the absolute value);
+   mode 2 (fixed) the caller's threshold. */
+static int set_defl(oparams *P, const double *H, long ld, int n, int mode, double thold)
+{
+    P->defl_mode = mode;
+    P->dthr = 0.0;
+    if (mode == 1) P->dthr = U * hess_fro(H, ld, n);
+    else if (mode == 2) {
+        if (!(thold >= 0.0) || !isfinite(thold)) return -1;
+        P->dthr = thold;
+    } else if (mode != 0) return -1;
+    return 0;
+}
+
+int hqr_oracle_aed_ex(double *H, double *Q, int64_t n, int64_t ld, int64_t ktop, int64_t kbot,
+                      int nw, double *cr, double *ci, int *ncand, int defl_mode, double defl_thold)
 {
     if (n < 0) return -3;
     if (ld < (n > 1 ? n : 1)) return -4;
@@ -876,7 +958,14 @@ int hqr_oracle_aed(double *H, double *Q, int64_t n, int64_t ld, int64_t ktop, in
     P.nibble = 14;
     P.kexsh = 6;
     P.smlnum = DBL_MIN * ((double)n / U);
+    if (set_defl(&P, H, ld, (int)n, defl_mode, defl_thold)) return -11;
     return aed_step(H, ld, (int)n, Q, ld, Q ? (int)n : 0, (int)ktop, (int)kbot, nw, cr, ci, ncand, &P);
+}
+
+int hqr_oracle_aed(double *H, double *Q, int64_t n, int64_t ld, int64_t ktop, int64_t kbot,
+                   int nw, double *cr, double *ci, int *ncand)
+{
+    return hqr_oracle_aed_ex(H, Q, n, ld, ktop, kbot, nw, cr, ci, ncand, 0, 0.0);
 }
 
 /* Main loop over the bottom unreduced block (Sec. 2.1 outline, Sec. 2.5). */
@@ -892,7 +981,7 @@ static int schur_driver(double *H, long ld, int n, double *Q, long ldq, int nq, 
     while (kbot >= ilo) {
         int ktop = ilo;
         for (int k = kbot; k > ilo; --k) {
-            if (H[IX(k, k - 1, ld)] == 0.0 || negligible(H, ld, k, ilo, kbot, P->smlnum)) {
+            if (H[IX(k, k - 1, ld)] == 0.0 || negligible(H, ld, k, ilo, kbot, P)) {
                 H[IX(k, k - 1, ld)] = 0.0;
                 ktop = k;
                 break;
@@ -968,7 +1057,7 @@ static int schur_driver(double *H, long ld, int n, double *Q, long ldq, int nq, 
             if (nsh < 2 || (nd > 0 && nsh < P->ns / 2)) continue; /* too few: AED again */
         }
         if (nsh < 2) continue;
-        long nrf = sweep(H, ld, n, Q, ldq, nq, ktop, kbot, nsh, sr, si, 1, P->smlnum);
+        long nrf = sweep(H, ld, n, Q, ldq, nq, ktop, kbot, nsh, sr, si, 1, P);
         if (P->stats) {
             P->stats[1]++;
             P->stats[2] += nsh;
@@ -982,8 +1071,9 @@ static int schur_driver(double *H, long ld, int n, double *Q, long ldq, int nq, 
     return info;
 }
 
-int hqr_oracle_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi,
-                        int ns, int nw, int nmin, int64_t itmax, int64_t *stats)
+int hqr_oracle_schur_defl(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi,
+                          int ns, int nw, int nmin, int64_t itmax, int64_t *stats, int defl_mode,
+                          double defl_thold)
 {
     if (n < 0) return -3;
     if (n == 0) return 0;
@@ -1007,6 +1097,7 @@ int hqr_oracle_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr,
     P.kexsh = 6;
     P.itmax = itmax > 0 ? (long)itmax : 30L * (n > 10 ? (long)n : 10L);
     P.smlnum = DBL_MIN * ((double)n / U);
+    if (set_defl(&P, H, ld, (int)n, defl_mode, defl_thold)) return -12;
     if (stats) memset(stats, 0, 6 * sizeof(int64_t));
     P.stats = stats;
     int info = schur_driver(H, ld, (int)n, Q, ld, Q ? (int)n : 0, 0, (int)n - 1, &P);
@@ -1028,6 +1119,12 @@ int hqr_oracle_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr,
         }
     }
     return info;
+}
+
+int hqr_oracle_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi,
+                        int ns, int nw, int nmin, int64_t itmax, int64_t *stats)
+{
+    return hqr_oracle_schur_defl(H, Q, n, ld, wr, wi, ns, nw, nmin, itmax, stats, 0, 0.0);
 }
 
 int hqr_oracle_schur(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi)

@@ -31,10 +31,20 @@ int hqr_oracle_schur(double *H, double *Q, int64_t n, int64_t ld, double *wr, do
 int hqr_oracle_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi,
                         int ns, int nw, int nmin, int64_t itmax, int64_t *stats);
 
+/* Same as hqr_oracle_schur_ex with the deflation conditions of Sec. 5.6
+   ("Comment regarding the deflation conditions and the accuracy"):
+   defl_mode 0 = LAPACK-style (item 1), 1 = norm-stable (item 2: subdiagonal
+   and spike entries <= u ||H||_F, the norm of the input's Hessenberg part),
+   2 = fixed (item 3: <= defl_thold).  Returns -12 for a bad mode/threshold. */
+int hqr_oracle_schur_defl(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi,
+                          int ns, int nw, int nmin, int64_t itmax, int64_t *stats, int defl_mode,
+                          double defl_thold);
+
 /* One multishift sweep (Sec. 2.3, tightly coupled chain) on the active block
    [ktop, kbot] (0-based, inclusive) with nshifts shifts (even; conjugate pairs
-   adjacent, bulge j uses shifts 2j, 2j+1).  vigilant != 0 enables vigilant
-   deflation checks behind each bulge. */
+   adjacent, bulge j uses shifts 2j, 2j+1).  vigilant != 0 enables the
+   vigilant deflation check of each subdiagonal entry once the topmost
+   bulge of the chain has passed it (LAPACK-style conditions). */
 int hqr_oracle_sweep(double *H, double *Q, int64_t n, int64_t ld, int64_t ktop, int64_t kbot,
                      int nshifts, const double *sr, const double *si, int vigilant);
 
@@ -53,6 +63,11 @@ int hqr_oracle_std2x2(double *a, double *b, double *c, double *d, double *cs, do
    undeflated candidates to cr/ci (count in *ncand). */
 int hqr_oracle_aed(double *H, double *Q, int64_t n, int64_t ld, int64_t ktop, int64_t kbot,
                    int nw, double *cr, double *ci, int *ncand);
+/* Same with the deflation conditions of Sec. 5.6 (defl_mode as for
+   hqr_oracle_schur_defl; the norm-stable threshold uses ||H||_F of the H
+   passed here).  Returns -11 for a bad mode/threshold. */
+int hqr_oracle_aed_ex(double *H, double *Q, int64_t n, int64_t ld, int64_t ktop, int64_t kbot,
+                      int nw, double *cr, double *ci, int *ncand, int defl_mode, double defl_thold);
 
 /* Gradient of a real loss of the eigenvalues: given the Schur form (T, Q) of H
    and g_i = dL/dRe(l_i) + i dL/dIm(l_i), writes dL/dH (n x n, leading dim ld).
@@ -67,6 +82,10 @@ void hqr_oracle_set_mutation(int m);
 
 /* Test hook: on != 0 makes every block swap report rejection (failure forcing). */
 void hqr_oracle_force_swap_failure(int on);
+
+/* Test hook: swaps rejected by the Bai-Demmel stability test since the last
+   reset (forced rejections not counted); reset != 0 clears the count. */
+int64_t hqr_oracle_swap_rejections(int reset);
 
 #ifdef __cplusplus
 }

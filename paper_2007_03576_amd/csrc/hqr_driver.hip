@@ -485,10 +485,17 @@ int sweep(Ctx &C, const View &V, int ktop, int kbot, int nsh, const double *sr, 
             cw.nb = gr.nb;
             cw.shift_off = gr.soff;
             cw.slot = take_slot(C);
+            // vigilant deflation (Sec. 3.2, 'push bulges'): only the windows of
+            // the last chain of the sweep scan the subdiagonal, behind its top
+            // bulge, where the entries are final for this sweep
             int tpos0 = gr.p0 - 3 * (gr.nb - 1);
             cw.vig_lo = std::max(ktop, tpos0);
             cw.vig_hi = std::min(kend, tpos0 + nsteps - 1);
             if (cw.vig_hi - cw.vig_lo + 1 > WMAX) cw.vig_lo = cw.vig_hi - WMAX + 1;
+            if (gi != ngroups - 1) {
+                cw.vig_lo = 1;
+                cw.vig_hi = 0;
+            }
             R.nwin++;
             gr.started = true;
             gr.p0 += nsteps;
