@@ -11,7 +11,9 @@
  *   - tightly coupled bulge chains chased in diagonal windows whose accumulated
  *     transformations are applied off-diagonal by matrix products: Sec. 2.3;
  *   - AED (window Schur form, spike test with eigenvalue reordering, Hessenberg
- *     restoration): Sec. 2.5; deflation conditions: Sec. 5.3 (LAPACK-style).
+ *     restoration): Sec. 2.5 "Aggressive early deflation"; deflation
+ *     conditions: Sec. 5.6 "Comment regarding the deflation conditions and
+ *     the accuracy" (LAPACK-style by default, norm-stable and fixed on request).
  *
  * Conventions shared by every entry point
  *   - Matrices are FP64, column major.  All matrix/vector pointers are DEVICE
@@ -40,7 +42,12 @@ extern "C" {
  *   itmax   iteration limit (AED steps + sweeps)             (Sec. 2.1)
  *   window  bulge-chasing window order (<= 96)              (Sec. 3.1, 'push bulges')
  *   bulges_per_window  bulges in one window chain
- *   defl_mode  0 = LAPACK-style conditions (the only mode implemented)
+ *   defl_mode  deflation conditions of Sec. 5.6: 0 = LAPACK-style (item 1:
+ *              Ahues-Tisseur subdiagonal test, spike entries against u|t_kk|
+ *              or u*h^, floor nu*n/u); 1 = norm-stable (item 2: subdiagonal
+ *              and spike entries against u*||H||_F, the Frobenius norm of the
+ *              input's Hessenberg part); 2 = fixed (item 3: against
+ *              defl_thold, finite and >= 0).  Other values are rejected.
  *   streams    1 = everything on the caller's stream; 2 = updates outside the
  *              active block and to Q on a second stream (Sec. 3.3 priorities)
  *   small_shifts  shifts per sweep of the one-workgroup solver (2 = Francis
@@ -115,15 +122,30 @@ int hqr_set_batched_launch(int32_t wg_per_cu, int32_t wide_n);
 /* Current values (host pointers); returns 0, or -1 for a NULL pointer. */
 int hqr_get_batched_launch(int32_t *wg_per_cu, int32_t *wide_n);
 
-/* Backward pass of the eigenvalues for a batch of Schur forms (T_i, Q_i) of
- * equal order n stored back to back, column major (T + i*n*n).  Given the cotangents
- * g = dL/dRe(lambda) + i dL/dIm(lambda) (gwr/gwi, n per matrix, ordered as
- * wr/wi), writes dH_i = Re(conj(Y) diag(conj(g)/(y^H x)) X^T) where X, Y hold
- * the right and left eigenvectors (Sec. 2 eigenvector relation x = Q y);
- * hess_mask != 0 zeroes entries below the first subdiagonal.  Asynchronous. */
-int hqr_eig_backward_batched(const double *T, const double *Q, int32_t n, int32_t batch,
-                             const double *wr, const double *wi, const double *gwr, const double *gwi,
-                             double *dH, int32_t hess_mask, void *stream);
+/* Backward pass of the eigenvalues (the differentiated form beside the
+ * solver) for a batch of Schur forms H_i = Q_i T_i Q_i^T, packed like the
+ * batched form: matrix i has order n[i] and T_i, Q_i and dH_i sit column major
+ * at T + offsets[i], Q + offsets[i], dH + offsets[i] with leading dimension
+ * n[i]; its eigenvalues (wr/wi, as returned by the solver: diagonal order,
+ * pairs adjacent with wi > 0 first) and cotangents g = dL/dRe(lambda) +
+ * i dL/dIm(lambda) (gwr/gwi) sit at offset e_i = n[0] + ... + n[i-1].
+ * Writes dH_i = Re(conj(Y) diag(conj(g)/(y^H x)) X^T), X and Y holding the
+ * right and left eigenvectors, obtained from T_i by quasi-triangular
+ * substitution and back-transformed by Q_i (the eigenvector relation of
+ * Sec. 2 "Modern QR algorithm and related work": the eigenvectors of H are
+ * Q times those of the Schur form).  hess_mask != 0 zeroes entries below the
+ * first subdiagonal (the forward reads only the Hessenberg part).
+ * All arrays are device arrays; 0 <= n[i] <= 8192; eigenvalues must be
+ * simple.  The call reads n and offsets back to the host (it synchronizes
+ * `stream` once at its start), then enqueues the kernels asynchronously.
+ * Workspace (10 n_i^2 + 1 doubles per matrix, in chunks of at most 2 GiB
+ * unless one matrix needs more) is kept per (device, stream) and grows only;
+ * calls on one stream are serialized.  Returns 0, -k for a bad argument k
+ * (a negative or too large order counts as argument 4, a negative offset as
+ * 3), or -1000-e for a HIP error e. */
+int hqr_eig_backward_batched(const double *T, const double *Q, const int64_t *offsets, const int32_t *n,
+                             int32_t batch, const double *wr, const double *wi, const double *gwr,
+                             const double *gwi, double *dH, int32_t hess_mask, void *stream);
 
 /* Timing and counters of the last hqr_schur call on this thread:
  * stats[0] AED steps, [1] sweeps, [2] shifts used, [3] eigenvalues deflated by

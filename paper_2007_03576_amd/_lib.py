@@ -50,7 +50,7 @@ def lib():
     L.hqr_schur_batched.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
     L.hqr_set_batched_launch.argtypes = [i32, i32]
     L.hqr_get_batched_launch.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
-    L.hqr_eig_backward_batched.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp, i32, vp]
+    L.hqr_eig_backward_batched.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, i32, vp]
     L.hqr_last_stats.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     L.hqr_finalize.argtypes = []
     L.hqr_profile_enable.argtypes = [ctypes.c_int]

@@ -64,7 +64,65 @@ class SchurEig(torch.autograd.Function):
         gr = g.real.contiguous().to(torch.float64)
         gi = g.imag.contiguous().to(torch.float64)
         dH = torch.empty_like(T)
-        check(lib().hqr_eig_backward_batched(_ptr(T), _ptr(Q), n, B, _ptr(wr), _ptr(wi), _ptr(gr), _ptr(gi),
-                                             _ptr(dH), 1, _stream()), "hqr_eig_backward_batched")
+        offs = torch.arange(B, dtype=torch.int64, device=T.device) * (n * n)
+        nn = torch.full((B,), n, dtype=torch.int32, device=T.device)
+        check(lib().hqr_eig_backward_batched(_ptr(T), _ptr(Q), _ptr(offs), _ptr(nn), B, _ptr(wr), _ptr(wi),
+                                             _ptr(gr), _ptr(gi), _ptr(dH), 1, _stream()),
+              "hqr_eig_backward_batched")
         out = dH.transpose(1, 2)  # column-major blocks -> logical matrices
         return out[0] if ctx.single else out
+
+
+class PackedSchurEig(torch.autograd.Function):
+    """Eigenvalues of matrices of uneven orders packed back to back column
+    major (the batched form's layout); forward hqr_schur_batched, backward
+    hqr_eig_backward_batched with the same offsets."""
+
+    @staticmethod
+    def forward(ctx, packed, sizes):
+        if packed.dtype != torch.float64 or not packed.is_cuda:
+            raise TypeError("PackedSchurEig expects a float64 CUDA tensor")
+        dev = packed.device
+        sz = [int(s) for s in sizes]
+        offs_l, eo_l = [0], [0]
+        for s in sz[:-1]:
+            offs_l.append(offs_l[-1] + s * s)
+            eo_l.append(eo_l[-1] + s)
+        offs = torch.tensor(offs_l, dtype=torch.int64, device=dev)
+        eo = torch.tensor(eo_l, dtype=torch.int64, device=dev)
+        nn = torch.tensor(sz, dtype=torch.int32, device=dev)
+        T = packed.detach().clone()
+        Q = torch.cat([torch.eye(s, dtype=torch.float64, device=dev).reshape(-1) for s in sz])
+        tot = sum(sz)
+        wr = torch.empty(max(tot, 1), dtype=torch.float64, device=dev)
+        wi = torch.empty_like(wr)
+        info = torch.empty(len(sz), dtype=torch.int32, device=dev)
+        check(lib().hqr_schur_batched(_ptr(T), _ptr(Q), _ptr(offs), _ptr(nn), len(sz), _ptr(wr), _ptr(wi),
+                                      _ptr(eo), _ptr(info), _stream()), "hqr_schur_batched")
+        if int(info.abs().max()) != 0:
+            raise RuntimeError("batched Schur reduction did not converge")
+        ctx.save_for_backward(T, Q, wr, wi, offs, nn)
+        return torch.complex(wr[:tot], wi[:tot])
+
+    @staticmethod
+    def backward(ctx, gw):
+        T, Q, wr, wi, offs, nn = ctx.saved_tensors
+        gr = torch.zeros_like(wr)
+        gi = torch.zeros_like(wi)
+        gr[:gw.numel()] = gw.real.to(torch.float64)
+        gi[:gw.numel()] = gw.imag.to(torch.float64)
+        dH = torch.empty_like(T)
+        check(lib().hqr_eig_backward_batched(_ptr(T), _ptr(Q), _ptr(offs), _ptr(nn), nn.numel(), _ptr(wr),
+                                             _ptr(wi), _ptr(gr), _ptr(gi), _ptr(dH), 1, _stream()),
+              "hqr_eig_backward_batched")
+        return dH, None
+
+
+def eigvals_uneven(mats):
+    """Differentiable eigenvalues of a list of square Hessenberg matrices of
+    any orders (one batched solve, one batched backward); returns a list of
+    complex eigenvalue tensors in diagonal order."""
+    sizes = tuple(int(m.shape[0]) for m in mats)
+    packed = torch.cat([m.transpose(0, 1).reshape(-1) for m in mats])
+    w = PackedSchurEig.apply(packed, sizes)
+    return list(torch.split(w, list(sizes)))

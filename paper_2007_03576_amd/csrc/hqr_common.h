@@ -16,6 +16,19 @@ constexpr int GMAX = 16;           // most bulges chased in one window
 constexpr int MAXWIN = 16;         // most windows in one chase round
 constexpr int MAXCAND = 1024;      // candidate eigenvalues returned by one AED step
 
+// Deflation conditions of the solver (Sec. 5.6, "Comment regarding the
+// deflation conditions and the accuracy").  thr < 0: LAPACK-style conditions
+// (item 1): the Ahues-Tisseur subdiagonal test and the u|t_kk| / u h^ spike
+// tests, floor smlnum = nu n / u.  thr >= 0: every subdiagonal entry and every
+// spike entry of a candidate block is compared with thr -- the norm-stable
+// conditions (item 2) with thr = u ||H||_F, or the fixed conditions (item 3)
+// with thr = the caller's threshold.  smlnum also floors the Bai-Demmel
+// acceptance test in every mode.
+struct Defl {
+    double smlnum;
+    double thr;
+};
+
 // Status record of one iteration, written by the device and read back by the
 // host (the only host synchronization per iteration).
 struct IterStatus {
@@ -86,17 +99,17 @@ struct UpdBatch {
 // then either reduce a small block to Schur form or perform an AED step with
 // window nw (<= MMAX).  Writes the factor (transposed, padded) to Ut.
 hipError_t launch_iter(double *H, int64_t ld, int n, int ilo, int kbot, int nw, int nmin,
-                       double smlnum, int64_t itmax, double *Ut, IterStatus *st, hipStream_t s, int nsmall);
+                       Defl dfl, int64_t itmax, double *Ut, IterStatus *st, hipStream_t s, int nsmall);
 // Locate the top of the active block only (st->ktop).
-hipError_t launch_find_block(double *H, int64_t ld, int ilo, int kbot, double smlnum, IterStatus *st,
+hipError_t launch_find_block(double *H, int64_t ld, int ilo, int kbot, Defl dfl, IterStatus *st,
                              hipStream_t s);
 // Chase round: one workgroup per window; U factors written transposed to Ubuf.
 hipError_t launch_chase(double *H, int64_t ld, const ChaseRound &r, const double *sr, const double *si,
-                        double smlnum, double *Ubuf, int64_t ustride, hipStream_t s);
+                        Defl dfl, double *Ubuf, int64_t ustride, hipStream_t s);
 // Deflation check of the bottom corner of a large AED window (T in global
 // memory, order nw; the corner has order wd <= MMAX) with reordering.
 hipError_t launch_corner_deflate(double *T, int64_t ldt, int nw, int wd, const double *V, int64_t ldv,
-                                 double s, double smlnum, double *Ut, IterStatus *st, int nforced,
+                                 double s, Defl dfl, double *Ut, IterStatus *st, int nforced,
                                  hipStream_t stream);
 // Hessenberg restoration of T(0:ns,0:ns) in global memory with the spike,
 // applied to T(0:ns, ns:nw) and to V (rows 0..nv-1).
@@ -108,11 +121,14 @@ hipError_t launch_window_copy(const double *H, int64_t ld, int kwtop, int nw, do
 // Eigenvalues of the diagonal blocks of a quasi-triangular T(0:m, 0:m).
 hipError_t launch_block_eigs(const double *T, int64_t ldt, int m, double *wr, double *wi,
                              hipStream_t s);
-// Standardize all 2x2 blocks of T (n x n) and extract eigenvalues, applying
-// the rotations to T and Q (may be NULL).
-hipError_t launch_finalize_ws(double *H, int64_t ld, int n, double *Q, double *wr, double *wi, double *ws,
+// Standardize the 2x2 blocks of T (n x n) in rows lo..n-1 and extract
+// eigenvalues, applying the rotations to T and Q (may be NULL).
+hipError_t launch_finalize_ws(double *H, int64_t ld, int n, int lo, double *Q, double *wr, double *wi, double *ws,
                               hipStream_t s);
 hipError_t launch_check_finite(const double *H, int64_t ld, int n, int *flag, hipStream_t s);
+// Frobenius norm of the Hessenberg part of H (n x n) into *out (device), for
+// the norm-stable deflation threshold; ws holds n doubles of scratch.
+hipError_t launch_hess_fro(const double *H, int64_t ld, int n, double *ws, double *out, hipStream_t s);
 hipError_t launch_zero_lower(double *H, int64_t ld, int n, hipStream_t s);
 hipError_t launch_transpose_pad(const double *V, int64_t ldv, int K, double *Ut, int K16,
                                 hipStream_t s);
@@ -122,9 +138,17 @@ constexpr int QHDR = 8;
 hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch,
                           double *wr, double *wi, const int64_t *eoff, int32_t *info, int32_t *queue,
                           int wg_per_cu, int wide_n, hipStream_t s);
-hipError_t launch_eig_backward(const double *T, const double *Q, int n, int batch, const double *wr,
-                               const double *wi, const double *gwr, const double *gwi, double *dH,
-                               int hess_mask, hipStream_t s);
+// Backward pass of the eigenvalues (hqr_grad.hip): one descriptor per matrix
+// (offsets in doubles of T_b/Q_b/dH_b, of its eigenvalue slots, of its
+// workspace from the chunk's base -- 10 n^2 + 1 doubles -- and its order).
+struct BwdDesc {
+    int64_t toff, eoff, woff;
+    int n, pad;
+};
+// One chunk of nb matrices (descriptors D, device), largest order nmax.
+hipError_t launch_eig_backward_chunk(const double *T, const double *Q, const BwdDesc *D, int nb, int nmax,
+                                     const double *wr, const double *wi, const double *gwr, const double *gwi,
+                                     double *dH, int hess_mask, double *ws, hipStream_t s);
 
 // ---- launchers (hqr_gemm.hip) ----
 hipError_t launch_updates(const UpdBatch &b, hipStream_t s);

@@ -43,6 +43,23 @@ struct QueueBuf {
 };
 std::map<std::pair<int, void *>, QueueBuf> g_queues;
 
+// Workspace of the backward pass, one per (device, stream), grow-only: host
+// staging (pinned) for the orders, offsets and descriptors, the device
+// descriptor table and the per-chunk workspace.  A call that fits the current
+// capacities allocates nothing; calls on one stream are serialized by mu.
+struct BwdWs {
+    std::mutex mu;
+    int32_t *h_n = nullptr;
+    int64_t *h_off = nullptr;
+    BwdDesc *h_desc = nullptr;
+    int64_t hcap = 0;
+    BwdDesc *d_desc = nullptr;
+    int64_t dcap = 0;
+    double *ws = nullptr;
+    size_t wcap = 0;
+};
+std::map<std::pair<int, void *>, BwdWs> g_bwd;
+
 // Launch shape of the batched global-memory grid: workgroups per CU, and the
 // order above which matrices go to half of that grid only.  Per bulge
 // position a workgroup touches about 176*n bytes of H and Q (n cache lines
@@ -58,6 +75,8 @@ struct Params {
     int streams;
     int nsmall; // shifts per multishift sweep of the one-workgroup solver (2 = double shift)
     int aed_ns, aed_nw, aed_nmin; // recursive solve of large AED windows (0 = automatic)
+    int defl_mode;                // 0 LAPACK-style, 1 norm-stable, 2 fixed (Sec. 5.6)
+    double defl_thold;            // threshold of the fixed conditions
 };
 
 // Reading of automatic parameters: LAPACK's documented shift-count table and
@@ -214,7 +233,7 @@ struct Ctx {
     Workspace *W;
     hipStream_t hi; // caller's stream: the critical path
     bool two;       // deferred updates on W->lo
-    double smlnum;
+    Defl dfl;       // deflation conditions
     Params P;
     int64_t *stats;
 };
@@ -507,7 +526,7 @@ int sweep(Ctx &C, const View &V, int ktop, int kbot, int nsh, const double *sr, 
         }
         if (R.nwin == 0) return -98;
         int pid = prof_begin(1, C.hi);
-        CK(launch_chase(V.H, V.ld, R, W.d_shift, W.d_shift + 2048, C.smlnum, W.ubuf, slot_ustride(), C.hi));
+        CK(launch_chase(V.H, V.ld, R, W.d_shift, W.d_shift + 2048, C.dfl, W.ubuf, slot_ustride(), C.hi));
         {
             double fl = 0.0, by = 0.0;
             for (int i = 0; i < R.nwin; ++i) {
@@ -636,7 +655,7 @@ int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd
         int slc = take_slot(C);
         double *Utc = slot_ptr(W, slc); // used on the critical stream only
         int pidc = prof_begin(3, C.hi);
-        CK(launch_corner_deflate(T, w, bot, wd, Vw, w, s, C.smlnum, Utc, W.st_dev, nfail, C.hi));
+        CK(launch_corner_deflate(T, w, bot, wd, Vw, w, s, C.dfl, Utc, W.st_dev, nfail, C.hi));
         prof_end(pidc, C.hi, 0.0, 0.0);
         if (read_status(C, 0)) return -1;
         const int c0 = W.st_host->kwtop, wdd = W.st_host->nw, halted = W.st_host->info;
@@ -712,7 +731,7 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
             int sl = take_slot(C);
             double *Ut = slot_ptr(W, sl);
             int pid = prof_begin(0, C.hi);
-            CK(launch_iter(V.H, V.ld, V.n, ilo, kbot, P.nw, P.nmin, C.smlnum, P.itmax, Ut, W.st_dev, C.hi, P.nsmall));
+            CK(launch_iter(V.H, V.ld, V.n, ilo, kbot, P.nw, P.nmin, C.dfl, P.itmax, Ut, W.st_dev, C.hi, P.nsmall));
             prof_end(pid, C.hi, 0.0, 0.0);
             if (C.stats) C.stats[6]++;
             if (read_status(C, nwp)) return -1;
@@ -720,14 +739,17 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
             prof_add_ticks(S);
             ktop = S.ktop;
             if (S.kind == 0) {
-                if (S.info > 0) {
-                    *info_out = S.info;
-                    return 0;
-                }
+                // the block was written back with the factor of the steps it
+                // took, converged or not: propagate it so that H = Q T Q^T holds
+                const int finfo = S.info;
                 if (C.stats) C.stats[4]++;
                 int rc = apply_factor(C, V, ktop, kbot, S.kwtop, S.nw, Ut);
                 release_slot(C, sl);
                 if (rc) return rc;
+                if (finfo > 0) {
+                    *info_out = finfo;
+                    return 0;
+                }
                 kbot = ktop - 1;
                 ndfl = 1;
                 continue;
@@ -743,7 +765,7 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
             }
             release_slot(C, sl);
         } else {
-            CK(launch_find_block(V.H, V.ld, ilo, kbot, C.smlnum, W.st_dev, C.hi));
+            CK(launch_find_block(V.H, V.ld, ilo, kbot, C.dfl, W.st_dev, C.hi));
             if (read_status(C, 0)) return -1;
             ktop = S.ktop;
             int nh = kbot - ktop + 1;
@@ -752,20 +774,21 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
                 int sl = take_slot(C);
                 double *Ut = slot_ptr(W, sl);
                 int pid = prof_begin(0, C.hi);
-                CK(launch_iter(V.H, V.ld, V.n, ilo, kbot, wv, P.nmin, C.smlnum, P.itmax, Ut, W.st_dev, C.hi, P.nsmall));
+                CK(launch_iter(V.H, V.ld, V.n, ilo, kbot, wv, P.nmin, C.dfl, P.itmax, Ut, W.st_dev, C.hi, P.nsmall));
                 prof_end(pid, C.hi, 0.0, 0.0);
                 if (read_status(C, MMAX)) return -1;
                 prof_set_flops(pid, S.beta);
                 prof_add_ticks(S);
                 if (S.kind == 0) {
-                    if (S.info > 0) {
-                        *info_out = S.info;
-                        return 0;
-                    }
+                    const int finfo = S.info;
                     if (C.stats) C.stats[4]++;
                     int rc = apply_factor(C, V, ktop, kbot, S.kwtop, S.nw, Ut);
                     release_slot(C, sl);
                     if (rc) return rc;
+                    if (finfo > 0) {
+                        *info_out = finfo;
+                        return 0;
+                    }
                     kbot = ktop - 1;
                     ndfl = 1;
                     continue;
@@ -879,6 +902,14 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
     return 0;
 }
 
+// Deflation mode 0 (LAPACK-style), 1 (norm-stable) or 2 (fixed, with a finite
+// threshold >= 0).
+bool defl_ok(const hqr_params *p)
+{
+    if (p->defl_mode == 0 || p->defl_mode == 1) return true;
+    return p->defl_mode == 2 && p->defl_thold >= 0.0 && std::isfinite(p->defl_thold);
+}
+
 Params resolve(const hqr_params *pp, int n)
 {
     hqr_params p;
@@ -905,6 +936,8 @@ Params resolve(const hqr_params *pp, int n)
     P.aed_nw = p.aed_nw > 0 ? std::max(4, std::min(p.aed_nw, MMAX)) : 0;
     P.aed_nmin = p.aed_nmin > 0 ? std::max(12, std::min(p.aed_nmin, MMAX)) : 0;
     if (P.nw < 2) P.nw = 2;
+    P.defl_mode = p.defl_mode;
+    P.defl_thold = p.defl_thold;
     return P;
 }
 
@@ -915,7 +948,7 @@ extern "C" {
 int hqr_set_params(const hqr_params *p)
 {
     if (!p) return -1;
-    if (p->ns < 0 || p->nw < 0 || p->nmin < 0 || p->window < 0 || p->defl_mode != 0) return -1;
+    if (p->ns < 0 || p->nw < 0 || p->nmin < 0 || p->window < 0 || !defl_ok(p)) return -1;
     std::lock_guard<std::mutex> lk(g_mu);
     g_params = *p;
     return 0;
@@ -940,7 +973,7 @@ int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double
     if (!wr) return -5;
     if (!wi) return -6;
     if (n > (int64_t)INT32_MAX / 2) return -3;
-    if (pp && pp->defl_mode != 0) return -8;
+    if (pp && !defl_ok(pp)) return -8;
     int dev = 0;
     CK(hipGetDevice(&dev));
     if (dev < 0 || dev >= 16) return -1000;
@@ -952,17 +985,33 @@ int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double
     C.W = &W;
     C.hi = (hipStream_t)stream;
     C.two = P.streams >= 2;
-    C.smlnum = DBL_MIN * ((double)n / DBL_EPSILON);
+    C.dfl.smlnum = DBL_MIN * ((double)n / DBL_EPSILON);
+    C.dfl.thr = (P.defl_mode == 2) ? P.defl_thold : -1.0;
     C.P = P;
     C.stats = t_stats;
+    if (W.fin_n < (size_t)n) {
+        if (W.fin) {
+            CK(hipDeviceSynchronize()); // an earlier call may still finish on another stream
+            CK(hipFree(W.fin));
+        }
+        W.fin = nullptr;
+        W.fin_n = 0;
+        CK(hipMalloc(&W.fin, sizeof(double) * 8 * (size_t)n));
+        W.fin_n = n;
+    }
     // argument check on the device: non-finite entries of the Hessenberg part
     CK(hipMemsetAsync(W.flag, 0, sizeof(int), C.hi));
     CK(launch_check_finite(H, ld, (int)n, W.flag, C.hi));
-    int flag = 0;
     CK(hipMemcpyAsync(&W.st_host->pad, W.flag, sizeof(int), hipMemcpyDeviceToHost, C.hi));
+    if (P.defl_mode == 1) {
+        // norm-stable conditions: u ||H||_F of the input (an orthogonal
+        // similarity keeps the norm, so one value serves the whole solve)
+        CK(launch_hess_fro(H, ld, (int)n, W.fin, &W.st_dev->beta, C.hi));
+        CK(hipMemcpyAsync(&W.st_host->beta, &W.st_dev->beta, sizeof(double), hipMemcpyDeviceToHost, C.hi));
+    }
     CK(hipStreamSynchronize(C.hi));
-    flag = W.st_host->pad;
-    if (flag) return -1;
+    if (W.st_host->pad) return -1;
+    if (P.defl_mode == 1) C.dfl.thr = DBL_EPSILON * W.st_host->beta;
     CK(launch_zero_lower(H, ld, (int)n, C.hi));
     View V{H, ld, (int)n, Q, ld, Q ? (int)n : 0};
     int info = 0;
@@ -977,13 +1026,8 @@ int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double
         CK(hipEventRecord(ev, W.lo));
         CK(hipStreamWaitEvent(C.hi, ev, 0));
     }
-    if (W.fin_n < (size_t)n) {
-        if (W.fin) hipFree(W.fin);
-        CK(hipMalloc(&W.fin, sizeof(double) * 8 * (size_t)n));
-        W.fin_n = n;
-    }
     int pidf = prof_begin(4, C.hi);
-    CK(launch_finalize_ws(H, ld, (int)n, Q, wr, wi, W.fin, C.hi));
+    CK(launch_finalize_ws(H, ld, (int)n, info > 0 ? info : 0, Q, wr, wi, W.fin, C.hi));
     prof_end(pidf, C.hi, 0.0, 0.0);
     CK(hipStreamSynchronize(C.hi));
     for (int i = 0; i < W.nslots; ++i) W.slot_used[i] = 0;
@@ -1074,6 +1118,17 @@ int hqr_finalize(void)
         hipFree(kv.second.p);
     }
     g_queues.clear();
+    for (auto &kv : g_bwd) {
+        hipSetDevice(kv.first.first);
+        hipDeviceSynchronize();
+        BwdWs &B = kv.second;
+        hipHostFree(B.h_n);
+        hipHostFree(B.h_off);
+        hipHostFree(B.h_desc);
+        hipFree(B.d_desc);
+        hipFree(B.ws);
+    }
+    g_bwd.clear();
     return 0;
 }
 
@@ -1136,21 +1191,97 @@ int hqr_get_batched_launch(int32_t *wg_per_cu, int32_t *wide_n)
 }
 
 
-int hqr_eig_backward_batched(const double *T, const double *Q, int32_t n, int32_t batch, const double *wr,
-                             const double *wi, const double *gwr, const double *gwi, double *dH, int32_t hess_mask,
-                             void *stream)
+int hqr_eig_backward_batched(const double *T, const double *Q, const int64_t *offsets, const int32_t *n,
+                             int32_t batch, const double *wr, const double *wi, const double *gwr,
+                             const double *gwi, double *dH, int32_t hess_mask, void *stream)
 {
     if (!T) return -1;
     if (!Q) return -2;
-    if (n < 0 || n > 8192) return -3;
-    if (batch < 0) return -4;
-    if (!wr) return -5;
-    if (!wi) return -6;
-    if (!gwr) return -7;
-    if (!gwi) return -8;
-    if (!dH) return -9;
-    if (n == 0 || batch == 0) return 0;
-    CK(launch_eig_backward(T, Q, n, batch, wr, wi, gwr, gwi, dH, hess_mask, (hipStream_t)stream));
+    if (!offsets) return -3;
+    if (!n) return -4;
+    if (batch < 0) return -5;
+    if (!wr) return -6;
+    if (!wi) return -7;
+    if (!gwr) return -8;
+    if (!gwi) return -9;
+    if (!dH) return -10;
+    if (batch == 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    BwdWs *B;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        B = &g_bwd[std::make_pair(dev, stream)];
+    }
+    std::lock_guard<std::mutex> call_lk(B->mu);
+    // the orders and offsets are read on the host to plan the chunks; the
+    // stream is synchronized here, so every earlier call on it (and its reads
+    // of the staging buffers) has finished
+    if (B->hcap < batch) {
+        if (B->h_n) CK(hipHostFree(B->h_n));
+        if (B->h_off) CK(hipHostFree(B->h_off));
+        if (B->h_desc) CK(hipHostFree(B->h_desc));
+        B->h_n = nullptr;
+        B->h_off = nullptr;
+        B->h_desc = nullptr;
+        B->hcap = 0;
+        CK(hipHostMalloc(&B->h_n, sizeof(int32_t) * (size_t)batch, hipHostMallocDefault));
+        CK(hipHostMalloc(&B->h_off, sizeof(int64_t) * (size_t)batch, hipHostMallocDefault));
+        CK(hipHostMalloc(&B->h_desc, sizeof(BwdDesc) * (size_t)batch, hipHostMallocDefault));
+        B->hcap = batch;
+    }
+    CK(hipMemcpyAsync(B->h_n, n, sizeof(int32_t) * (size_t)batch, hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(B->h_off, offsets, sizeof(int64_t) * (size_t)batch, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    // descriptors and chunks: a chunk's workspace stays within 2 GiB unless a
+    // single matrix needs more
+    const size_t cap_doubles = ((size_t)1 << 31) / sizeof(double);
+    int64_t eo = 0;
+    size_t need_max = 0, run = 0;
+    for (int32_t b = 0; b < batch; ++b) {
+        const int32_t nb_ = B->h_n[b];
+        if (nb_ < 0 || nb_ > 8192) return -4;
+        if (B->h_off[b] < 0) return -3;
+        const size_t wsz = 10 * (size_t)nb_ * nb_ + 1;
+        if (run > 0 && run + wsz > cap_doubles) run = 0;
+        BwdDesc &d = B->h_desc[b];
+        d.toff = B->h_off[b];
+        d.eoff = eo;
+        d.woff = (int64_t)run;
+        d.n = nb_;
+        d.pad = 0;
+        run += wsz;
+        need_max = std::max(need_max, run);
+        eo += nb_;
+    }
+    if (B->dcap < batch) {
+        if (B->d_desc) CK(hipFree(B->d_desc));
+        B->d_desc = nullptr;
+        B->dcap = 0;
+        CK(hipMalloc(&B->d_desc, sizeof(BwdDesc) * (size_t)batch));
+        B->dcap = batch;
+    }
+    if (B->wcap < need_max) {
+        if (B->ws) CK(hipFree(B->ws));
+        B->ws = nullptr;
+        B->wcap = 0;
+        CK(hipMalloc(&B->ws, sizeof(double) * need_max));
+        B->wcap = need_max;
+    }
+    CK(hipMemcpyAsync(B->d_desc, B->h_desc, sizeof(BwdDesc) * (size_t)batch, hipMemcpyHostToDevice, st));
+    int32_t b0 = 0;
+    while (b0 < batch) {
+        int32_t b1 = b0 + 1;
+        int nmax = B->h_n[b0];
+        while (b1 < batch && B->h_desc[b1].woff != 0) {
+            nmax = std::max(nmax, (int)B->h_n[b1]);
+            ++b1;
+        }
+        CK(launch_eig_backward_chunk(T, Q, B->d_desc + b0, b1 - b0, nmax, wr, wi, gwr, gwi, dH, hess_mask,
+                                     B->ws, st));
+        b0 = b1;
+    }
     return 0;
 }
 

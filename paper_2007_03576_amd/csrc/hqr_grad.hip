@@ -20,11 +20,20 @@ namespace hqr {
 typedef double dbl4g __attribute__((ext_vector_type(4)));
 constexpr double kUg = 2.220446049250313080847e-16;
 
+// Per-matrix descriptor of a backward call: offsets of T_b / Q_b / dH_b
+// (doubles), of its eigenvalues and cotangents, of its workspace (doubles from
+// the chunk's base), and its order.
+//   workspace of matrix b (n = n_b): Ys, Zs (2n x n each: right / left
+//   eigenvectors of T, real parts in rows 0..n-1, imaginary in n..2n-1),
+//   X, Yl, W (n x 2n each), then max|T_b|; 10 n^2 + 1 doubles.
+
 // max |T| per matrix (for the pivot floor of the substitutions)
-__global__ void k_tnorm(const double *T, int n, double *tn)
+__global__ void k_tnorm(const double *T, const BwdDesc *D, double *ws)
 {
     __shared__ double red[256];
-    const double *Tb = T + (int64_t)blockIdx.x * n * n;
+    const BwdDesc d = D[blockIdx.x];
+    const int n = d.n;
+    const double *Tb = T + d.toff;
     double m = 0.0;
     for (int64_t i = threadIdx.x; i < (int64_t)n * n; i += blockDim.x) m = fmax(m, fabs(Tb[i]));
     red[threadIdx.x] = m;
@@ -33,7 +42,7 @@ __global__ void k_tnorm(const double *T, int n, double *tn)
         if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) tn[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) ws[d.woff + 10 * (int64_t)n * n] = red[0];
 }
 
 __device__ inline void cdiv(double ar, double ai, double br, double bi, double &qr, double &qi)
@@ -73,18 +82,21 @@ __device__ inline void solve2(double b00, double b01, double b10, double b11, do
 // Right (Y) and left (Z) eigenvectors of the quasi-triangular T_b, one lane
 // per eigenvalue.  Storage: per matrix a 2n x n column-major array with the
 // real part of vector e, entry l at [e + l*2n] and the imaginary part at
-// [n + e + l*2n] (lanes of a wave touch consecutive addresses).
-__global__ void __launch_bounds__(64) k_eigvec(const double *T, int n, const double *wr, const double *wi,
-                                               const double *tn, double *Ys, double *Zs)
+// [n + e + l*2n] (lanes of a wave touch consecutive addresses).  Grid:
+// (ceil(max n / 64), matrices); blocks past a matrix's order return at once.
+__global__ void __launch_bounds__(64) k_eigvec(const double *T, const BwdDesc *D, const double *wr,
+                                               const double *wi, double *ws)
 {
-    const int b = blockIdx.y;
-    const double *Tb = T + (int64_t)b * n * n;
+    const BwdDesc d = D[blockIdx.y];
+    const int n = d.n;
+    if ((int)blockIdx.x * 64 >= n) return; // whole block past the order (uniform)
+    const double *Tb = T + d.toff;
     const int e = blockIdx.x * 64 + threadIdx.x;
     const bool act = e < n;
     const int64_t ld2 = 2 * (int64_t)n;
-    double *Y = Ys + (int64_t)b * ld2 * n;
-    double *Z = Zs + (int64_t)b * ld2 * n;
-    const double smin = fmax(kUg * tn[b], DBL_MIN);
+    double *Y = ws + d.woff;
+    double *Z = Y + 2 * (int64_t)n * n;
+    const double smin = fmax(kUg * ws[d.woff + 10 * (int64_t)n * n], DBL_MIN);
     int k = 0, sz = 1;
     double lr = 0.0, li = 0.0;
     if (act) {
@@ -92,8 +104,8 @@ __global__ void __launch_bounds__(64) k_eigvec(const double *T, int n, const dou
         bool first = (e + 1 < n && Tb[(e + 1) + (int64_t)e * n] != 0.0);
         k = second ? e - 1 : e;
         sz = (first || second) ? 2 : 1;
-        lr = wr[(int64_t)b * n + e];
-        li = wi[(int64_t)b * n + e];
+        lr = wr[d.eoff + e];
+        li = wi[d.eoff + e];
         for (int l = 0; l < n; ++l) {
             Y[e + l * ld2] = 0.0;
             Y[n + e + l * ld2] = 0.0;
@@ -163,8 +175,6 @@ __global__ void __launch_bounds__(64) k_eigvec(const double *T, int n, const dou
     while (j < n) {
         bool two = (j + 1 < n && Tb[(j + 1) + (int64_t)j * n] != 0.0);
         bool on = act && j >= k + sz;
-        int lo = act ? k : kmin;
-        (void)lo;
         double s0r = 0.0, s0i = 0.0, s1r = 0.0, s1i = 0.0;
         int lstart = max(0, kmin - 2);
         for (int l = lstart; l < j; ++l) {
@@ -205,20 +215,50 @@ __global__ void __launch_bounds__(64) k_eigvec(const double *T, int n, const dou
     }
 }
 
-// Batched C = op(A) op(B) (m x nn, inner dimension kk), FP64 MFMA.
-// opA/opB: 0 = as stored (column major), 1 = transposed.
+// Batched products of the backward pass on FP64 MFMA, 64 x 64 output tiles
+// per workgroup, per-matrix shapes from the descriptors:
+//   which 0: X  = Q Ys^T   (n x 2n, inner n)
+//   which 1: Yl = Q Zs^T   (n x 2n, inner n)
+//   which 2: dH = W X^T    (n x n, inner 2n)
+// Grid: (ceil(max rows / 64), ceil(max cols / 64), matrices); tiles past a
+// matrix's shape return before the first barrier.
 constexpr int GT = 64, GK = 16, GPAD = 4;
-__global__ void __launch_bounds__(256) k_gemm_batched(int m, int nn, int kk, const double *A, int64_t lda,
-                                                      int64_t sA, int opA, const double *B, int64_t ldb,
-                                                      int64_t sB, int opB, double *C, int64_t ldc, int64_t sC)
+__global__ void __launch_bounds__(256) k_gemm_bwd(int which, const double *Qg, const BwdDesc *D, double *ws,
+                                                  double *dH)
 {
     __shared__ double As[GK][GT + GPAD];
     __shared__ double Bs[GK][GT + GPAD];
-    const int bz = blockIdx.z;
-    A += (int64_t)bz * sA;
-    B += (int64_t)bz * sB;
-    C += (int64_t)bz * sC;
+    const BwdDesc d = D[blockIdx.z];
+    const int n = d.n;
+    const int64_t nn = (int64_t)n * n;
+    double *wb = ws + d.woff;
+    const double *A, *B;
+    double *C;
+    int m, nc, kk;
+    int64_t lda, ldb, ldc;
+    if (which < 2) {
+        A = Qg + d.toff;
+        lda = n;
+        B = wb + (which == 0 ? 0 : 2 * nn); // Ys or Zs, 2n x n, used transposed
+        ldb = 2 * (int64_t)n;
+        C = wb + (which == 0 ? 4 * nn : 6 * nn); // X or Yl
+        ldc = n;
+        m = n;
+        nc = 2 * n;
+        kk = n;
+    } else {
+        A = wb + 8 * nn; // W, n x 2n
+        lda = n;
+        B = wb + 4 * nn; // X, n x 2n, used transposed
+        ldb = n;
+        C = dH + d.toff;
+        ldc = n;
+        m = n;
+        nc = n;
+        kk = 2 * n;
+    }
     const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+    if (m0 >= m || n0 >= nc) return; // uniform per workgroup
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
     const int l16 = lane & 15, lq = lane >> 4;
@@ -227,30 +267,14 @@ __global__ void __launch_bounds__(256) k_gemm_batched(int m, int nn, int kk, con
         for (int c = 0; c < 2; ++c) acc[a][c] = (dbl4g){0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < kk; k0 += GK) {
         for (int it = tid; it < GT * GK; it += 256) {
-            int mi, ki;
-            if (opA == 0) {
-                mi = it % GT;
-                ki = it / GT;
-            } else {
-                ki = it % GK;
-                mi = it / GK;
-            }
-            int gm = m0 + mi, gk = k0 + ki;
-            double v = 0.0;
-            if (gm < m && gk < kk) v = (opA == 0) ? A[gm + (int64_t)gk * lda] : A[gk + (int64_t)gm * lda];
-            As[ki][mi] = v;
-            int nj, kj;
-            if (opB == 0) {
-                kj = it % GK;
-                nj = it / GK;
-            } else {
-                nj = it % GT;
-                kj = it / GT;
-            }
-            int gn = n0 + nj, gk2 = k0 + kj;
-            double w = 0.0;
-            if (gn < nn && gk2 < kk) w = (opB == 0) ? B[gk2 + (int64_t)gn * ldb] : B[gn + (int64_t)gk2 * ldb];
-            Bs[kj][nj] = w;
+            // A as stored (column major): rows along the tile's first index
+            const int mi = it % GT, ki = it / GT;
+            const int gm = m0 + mi, gk = k0 + ki;
+            As[ki][mi] = (gm < m && gk < kk) ? A[gm + (int64_t)gk * lda] : 0.0;
+            // B used transposed: B^T(k, j) = B[j + k*ldb]
+            const int nj = it % GT, kj = it / GT;
+            const int gn = n0 + nj, gk2 = k0 + kj;
+            Bs[kj][nj] = (gn < nc && gk2 < kk) ? B[gn + (int64_t)gk2 * ldb] : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -270,20 +294,23 @@ __global__ void __launch_bounds__(256) k_gemm_batched(int m, int nn, int kk, con
             for (int r = 0; r < 4; ++r) {
                 int gm = m0 + wm + a * 16 + lq + 4 * r;
                 int gn = n0 + wn + c * 16 + l16;
-                if (gm < m && gn < nn) C[gm + (int64_t)gn * ldc] = acc[a][c][r];
+                if (gm < m && gn < nc) C[gm + (int64_t)gn * ldc] = acc[a][c][r];
             }
 }
 
 // c_i = conj(g_i) / (y_i^H x_i) and the columns of W = [A1, -A2]:
 //   A1 = Yr diag(cr) + Yi diag(ci),  A2 = Yr diag(ci) - Yi diag(cr)
 // X = [Xr | Xi], Yl = [Yr | Yi] are n x 2n (ld n).  One block per (i, b).
-__global__ void k_coef(int n, const double *X, const double *Yl, const double *gwr, const double *gwi, double *W)
+__global__ void k_coef(const BwdDesc *D, const double *gwr, const double *gwi, double *ws)
 {
     __shared__ double red[2][256];
-    const int i = blockIdx.x, b = blockIdx.y;
-    const int64_t nn2 = 2 * (int64_t)n * n;
-    const double *Xb = X + b * nn2, *Yb = Yl + b * nn2;
-    double *Wb = W + b * nn2;
+    const BwdDesc d = D[blockIdx.y];
+    const int n = d.n;
+    const int i = blockIdx.x;
+    if (i >= n) return; // uniform per workgroup
+    const int64_t nn = (int64_t)n * n;
+    const double *Xb = ws + d.woff + 4 * nn, *Yb = ws + d.woff + 6 * nn;
+    double *Wb = ws + d.woff + 8 * nn;
     double dr = 0.0, di = 0.0;
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
         double yr = Yb[a + (int64_t)i * n], yi = Yb[a + (int64_t)(n + i) * n];
@@ -303,7 +330,7 @@ __global__ void k_coef(int n, const double *X, const double *Yl, const double *g
     }
     dr = red[0][0];
     di = red[1][0];
-    double gr = gwr[(int64_t)b * n + i], gi = -gwi[(int64_t)b * n + i]; // conj(g)
+    double gr = gwr[d.eoff + i], gi = -gwi[d.eoff + i]; // conj(g)
     double cr, ci;
     cdiv(gr, gi, dr, di, cr, ci);
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
@@ -313,66 +340,30 @@ __global__ void k_coef(int n, const double *X, const double *Yl, const double *g
     }
 }
 
-__global__ void k_hess_mask(int n, double *dH)
+__global__ void k_hess_mask(const BwdDesc *D, double *dH)
 {
-    const int c = blockIdx.x, b = blockIdx.y;
-    double *D = dH + (int64_t)b * n * n;
-    for (int r = c + 2 + threadIdx.x; r < n; r += blockDim.x) D[r + (int64_t)c * n] = 0.0;
+    const BwdDesc d = D[blockIdx.y];
+    const int n = d.n, c = blockIdx.x;
+    if (c >= n) return;
+    double *Db = dH + d.toff;
+    for (int r = c + 2 + threadIdx.x; r < n; r += blockDim.x) Db[r + (int64_t)c * n] = 0.0;
 }
 
-static hipError_t gemm(int m, int nn, int kk, const double *A, int64_t lda, int64_t sA, int opA, const double *B,
-                       int64_t ldb, int64_t sB, int opB, double *C, int64_t ldc, int64_t sC, int batch,
-                       hipStream_t s)
+hipError_t launch_eig_backward_chunk(const double *T, const double *Q, const BwdDesc *D, int nb, int nmax,
+                                     const double *wr, const double *wi, const double *gwr, const double *gwi,
+                                     double *dH, int hess_mask, double *ws, hipStream_t s)
 {
-    dim3 grid((m + GT - 1) / GT, (nn + GT - 1) / GT, batch);
-    hipLaunchKernelGGL(k_gemm_batched, grid, dim3(256), 0, s, m, nn, kk, A, lda, sA, opA, B, ldb, sB, opB, C, ldc,
-                       sC);
-    return hipGetLastError();
-}
-
-namespace {
-double *g_gws = nullptr;
-size_t g_gws_bytes = 0;
-}
-
-hipError_t launch_eig_backward(const double *T, const double *Q, int n, int batch, const double *wr,
-                               const double *wi, const double *gwr, const double *gwi, double *dH, int hess_mask,
-                               hipStream_t s)
-{
-    const int64_t nn = (int64_t)n * n;
-    // per matrix: Ys, Zs (2n x n), X, Yl, W (n x 2n) and the norm
-    const size_t per = (size_t)(10 * nn + 1) * sizeof(double);
-    int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)batch, ((size_t)1 << 31) / per));
-    size_t need = per * chunk;
-    if (need > g_gws_bytes) {
-        if (g_gws) {
-            hipError_t e = hipFree(g_gws);
-            if (e != hipSuccess) return e;
-        }
-        g_gws = nullptr;
-        hipError_t e = hipMalloc(&g_gws, need);
-        if (e != hipSuccess) return e;
-        g_gws_bytes = need;
-    }
-    for (int b0 = 0; b0 < batch; b0 += chunk) {
-        int nb = std::min(chunk, batch - b0);
-        double *Ys = g_gws, *Zs = Ys + 2 * nn * chunk, *X = Zs + 2 * nn * chunk, *Yl = X + 2 * nn * chunk;
-        double *W = Yl + 2 * nn * chunk, *tn = W + 2 * nn * chunk;
-        const double *Tb = T + b0 * nn, *Qb = Q + b0 * nn;
-        hipLaunchKernelGGL(k_tnorm, dim3(nb), dim3(256), 0, s, Tb, n, tn);
-        hipLaunchKernelGGL(k_eigvec, dim3((n + 63) / 64, nb), dim3(64), 0, s, Tb, n, wr + (int64_t)b0 * n,
-                           wi + (int64_t)b0 * n, tn, Ys, Zs);
-        hipError_t e;
-        // X = Q Ys^T, Yl = Q Zs^T   (Ys is 2n x n, ld 2n)
-        if ((e = gemm(n, 2 * n, n, Qb, n, nn, 0, Ys, 2 * n, 2 * nn, 1, X, n, 2 * nn, nb, s)) != hipSuccess) return e;
-        if ((e = gemm(n, 2 * n, n, Qb, n, nn, 0, Zs, 2 * n, 2 * nn, 1, Yl, n, 2 * nn, nb, s)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_coef, dim3(n, nb), dim3(256), 0, s, n, X, Yl, gwr + (int64_t)b0 * n,
-                           gwi + (int64_t)b0 * n, W);
-        // dH = W X^T (K = 2n)
-        if ((e = gemm(n, n, 2 * n, W, n, 2 * nn, 0, X, n, 2 * nn, 1, dH + b0 * nn, n, nn, nb, s)) != hipSuccess)
-            return e;
-        if (hess_mask) hipLaunchKernelGGL(k_hess_mask, dim3(n, nb), dim3(64), 0, s, n, dH + b0 * nn);
-    }
+    if (nb <= 0 || nmax <= 0) return hipSuccess;
+    const int tiles = (nmax + GT - 1) / GT, tiles2 = (2 * nmax + GT - 1) / GT;
+    hipLaunchKernelGGL(k_tnorm, dim3(nb), dim3(256), 0, s, T, D, ws);
+    hipLaunchKernelGGL(k_eigvec, dim3((nmax + 63) / 64, nb), dim3(64), 0, s, T, D, wr, wi, ws);
+    // X = Q Ys^T, Yl = Q Zs^T
+    hipLaunchKernelGGL(k_gemm_bwd, dim3(tiles, tiles2, nb), dim3(256), 0, s, 0, Q, D, ws, dH);
+    hipLaunchKernelGGL(k_gemm_bwd, dim3(tiles, tiles2, nb), dim3(256), 0, s, 1, Q, D, ws, dH);
+    hipLaunchKernelGGL(k_coef, dim3(nmax, nb), dim3(256), 0, s, D, gwr, gwi, ws);
+    // dH = W X^T
+    hipLaunchKernelGGL(k_gemm_bwd, dim3(tiles, tiles, nb), dim3(256), 0, s, 2, Q, D, ws, dH);
+    if (hess_mask) hipLaunchKernelGGL(k_hess_mask, dim3(nmax, nb), dim3(64), 0, s, D, dH);
     return hipGetLastError();
 }
 

@@ -112,11 +112,16 @@ __device__ inline void house3f(int m, double x0, double x1, double x2, double &v
     beta = b;
 }
 
-// Ahues-Tisseur small-subdiagonal test of A[k,k-1] inside [lo,hi].
-__device__ inline bool small_sub(const double *A, int lda, int k, int lo, int hi, double smlnum)
+// Vigilant (subdiagonal) deflation test of A[k,k-1] inside [lo,hi].
+// LAPACK-style conditions: the Ahues-Tisseur criterion; norm-stable and fixed
+// conditions: |A[k,k-1]| <= thr (Sec. 5.6, items 2 and 3).  LD is int for LDS
+// and int64_t for global memory.
+template <typename LD>
+__device__ inline bool small_sub(const double *A, LD lda, int k, int lo, int hi, const Defl &dfl)
 {
     double h21 = fabs(A[k + (k - 1) * lda]);
-    if (h21 <= smlnum) return true;
+    if (dfl.thr >= 0.0) return h21 <= dfl.thr;
+    if (h21 <= dfl.smlnum) return true;
     double h11 = A[(k - 1) + (k - 1) * lda], h22 = A[k + k * lda];
     double tst = fabs(h11) + fabs(h22);
     if (tst == 0.0) {
@@ -129,7 +134,7 @@ __device__ inline bool small_sub(const double *A, int lda, int k, int lo, int hi
     double d = fabs(h11 - h22);
     double aa = fmax(fabs(h22), d), bb = fmin(fabs(h22), d);
     double s = aa + ab;
-    return ba * (ab / s) <= fmax(smlnum, kU * (bb * (aa / s)));
+    return ba * (ab / s) <= fmax(dfl.smlnum, kU * (bb * (aa / s)));
 }
 
 // Rotation G = [[cs,-sn],[sn,cs]] that standardizes [[a,b],[c,d]] (G^T B G):
@@ -902,12 +907,12 @@ __device__ __forceinline__ void chase_la(SmemCore &S, double *A, int lda, int kt
 
 // Largest l in (lo,hi] whose subdiagonal A[l,l-1] is zero or negligible
 // (then set to zero); lo if there is none.
-__device__ __forceinline__ int find_split(SmemCore &S, double *A, int lda, int lo, int hi, double smlnum)
+__device__ __forceinline__ int find_split(SmemCore &S, double *A, int lda, int lo, int hi, const Defl &dfl)
 {
     if (threadIdx.x == 0) S.ic[0] = lo;
     __syncthreads();
     for (int l = hi - (int)threadIdx.x; l > lo; l -= NT) {
-        if (A[l + (l - 1) * lda] == 0.0 || small_sub(A, lda, l, lo, hi, smlnum)) {
+        if (A[l + (l - 1) * lda] == 0.0 || small_sub(A, lda, l, lo, hi, dfl)) {
             atomicMax(&S.ic[0], l);
             break;
         }
@@ -1020,7 +1025,7 @@ __device__ __forceinline__ void ds_step(SmemCore &S, double *A, int lda, int m, 
 
 // Francis double-shift QR on the whole matrix A (order m, full T), Z accumulates.
 // Returns 0 or 1 + the bottom row of the block that did not converge.
-__device__ __forceinline__ int qr_ds(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, double smlnum,
+__device__ __forceinline__ int qr_ds(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, const Defl &dfl,
                      int64_t itmax_in)
 {
     int64_t itmax = 30 * (int64_t)max(10, m);
@@ -1030,7 +1035,7 @@ __device__ __forceinline__ int qr_ds(SmemCore &S, double *A, int lda, int m, dou
     while (i >= 0) {
         int its = 0, l;
         for (;;) {
-            l = find_split(S, A, lda, 0, i, smlnum);
+            l = find_split(S, A, lda, 0, i, dfl);
             if (l >= i - 1) break;
             if (total >= itmax) return i + 1;
             ds_step(S, A, lda, m, Z, ldz, nz, l, i, its);
@@ -1052,10 +1057,10 @@ __device__ __forceinline__ int qr_ds(SmemCore &S, double *A, int lda, int m, dou
 // become the shifts of a chain of ns/2 tightly coupled bulges chased through
 // the block in one pass (Sec. 2.3); otherwise, and at the exceptional-shift
 // iterations, a double-shift step.  nsmax <= 2 gives the plain Francis QR.
-__device__ __forceinline__ int qr_small(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, double smlnum,
+__device__ __forceinline__ int qr_small(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, const Defl &dfl,
                         int64_t itmax_in, int nsmax = 2)
 {
-    if (nsmax <= 2) return qr_ds(S, A, lda, m, Z, ldz, nz, smlnum, itmax_in);
+    if (nsmax <= 2) return qr_ds(S, A, lda, m, Z, ldz, nz, dfl, itmax_in);
     nsmax = min(nsmax, 16) & ~1;
     int64_t itmax = 30 * (int64_t)max(10, m);
     if (itmax_in > 0 && itmax_in < itmax) itmax = itmax_in;
@@ -1064,7 +1069,7 @@ __device__ __forceinline__ int qr_small(SmemCore &S, double *A, int lda, int m, 
     while (i >= 0) {
         int its = 0, l;
         for (;;) {
-            l = find_split(S, A, lda, 0, i, smlnum);
+            l = find_split(S, A, lda, 0, i, dfl);
             if (l >= i - 1) break;
             if (total >= itmax) return i + 1;
             const int nh = i - l + 1;
@@ -1077,7 +1082,7 @@ __device__ __forceinline__ int qr_small(SmemCore &S, double *A, int lda, int m, 
                     S.shb[r + c * ns] = (r <= c + 1) ? A[(j0 + r) + (j0 + c) * lda] : 0.0;
                 }
                 __syncthreads();
-                int inf = qr_ds(S, S.shb, ns, ns, S.shb, ns, 0, smlnum, 0); // no Z rows (nz = 0)
+                int inf = qr_ds(S, S.shb, ns, ns, S.shb, ns, 0, dfl, 0); // no Z rows (nz = 0)
                 if (threadIdx.x == 0) {
                     // pair the eigenvalues of the converged part, bottom first
                     int cnt = 0;
@@ -1449,8 +1454,9 @@ __device__ bool swap_xform(double *Tw, int ldt, int j, double smlnum, double *Go
 // the deflated bottom counts as undeflated.  Returns the number of undeflated
 // leading rows.
 __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int sprow,
-                           double spscale, int ilst0, double smlnum, int nforced = 0)
+                           double spscale, int ilst0, const Defl &dfl, int nforced = 0)
 {
+    const double smlnum = dfl.smlnum;
     ReorderState &R = S.ro;
     const int tid = threadIdx.x;
     if (tid == 0) {
@@ -1510,7 +1516,11 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
                     const int csz = two ? 2 : 1, k = ns - 1, cand = ns - csz;
                     if (cand < lim2) break; // still touched by the move above it
                     bool defl;
-                    if (!two) {
+                    if (dfl.thr >= 0.0) {
+                        // norm-stable / fixed conditions: each spike entry of the block
+                        defl = fabs(spscale * Z[sprow + k * ldz]) <= dfl.thr;
+                        if (two) defl = defl && fabs(spscale * Z[sprow + (k - 1) * ldz]) <= dfl.thr;
+                    } else if (!two) {
                         const double foo = fabs(T[k + k * ldt]);
                         defl = fabs(spscale * Z[sprow + k * ldz]) <= fmax(smlnum, kU * foo);
                     } else {
@@ -1842,37 +1852,14 @@ __device__ __forceinline__ void identity_lds(double *Z, int ldz, int m, int rows
 // ---------------------------------------------------------------------------
 // kernels
 
-__global__ void __launch_bounds__(NT) k_find_block(double *H, int64_t ld, int ilo, int kbot, double smlnum,
+__global__ void __launch_bounds__(NT) k_find_block(double *H, int64_t ld, int ilo, int kbot, Defl dfl,
                                                    IterStatus *st)
 {
     __shared__ int best;
     if (threadIdx.x == 0) best = ilo;
     __syncthreads();
     for (int l = kbot - (int)threadIdx.x; l > ilo; l -= NT) {
-        double h = H[l + (int64_t)(l - 1) * ld];
-        bool hit = (h == 0.0);
-        if (!hit) {
-            // Ahues-Tisseur test on global memory
-            double h21 = fabs(h);
-            if (h21 <= smlnum) hit = true;
-            else {
-                double h11 = H[(l - 1) + (int64_t)(l - 1) * ld], h22 = H[l + (int64_t)l * ld];
-                double tst = fabs(h11) + fabs(h22);
-                if (tst == 0.0) {
-                    if (l - 2 >= ilo) tst += fabs(H[(l - 1) + (int64_t)(l - 2) * ld]);
-                    if (l + 1 <= kbot) tst += fabs(H[(l + 1) + (int64_t)l * ld]);
-                }
-                if (h21 <= kU * tst) {
-                    double h12 = fabs(H[(l - 1) + (int64_t)l * ld]);
-                    double ab = fmax(h21, h12), ba = fmin(h21, h12);
-                    double d = fabs(h11 - h22);
-                    double aa = fmax(fabs(h22), d), bb = fmin(fabs(h22), d);
-                    double s = aa + ab;
-                    hit = ba * (ab / s) <= fmax(smlnum, kU * (bb * (aa / s)));
-                }
-            }
-        }
-        if (hit) {
+        if (H[l + (int64_t)(l - 1) * ld] == 0.0 || small_sub(H, ld, l, ilo, kbot, dfl)) {
             atomicMax(&best, l);
             break;
         }
@@ -1886,7 +1873,7 @@ __global__ void __launch_bounds__(NT) k_find_block(double *H, int64_t ld, int il
 }
 
 __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int ilo, int kbot, int nw, int nmin,
-                                             double smlnum, int64_t itmax, double *Ut, IterStatus *st, int nsmall)
+                                             Defl dfl, int64_t itmax, double *Ut, IterStatus *st, int nsmall)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem &S = *reinterpret_cast<Smem *>(smem_raw);
@@ -1900,29 +1887,7 @@ __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int i
     }
     __syncthreads();
     for (int l = kbot - tid; l > ilo; l -= NT) {
-        double h = H[l + (int64_t)(l - 1) * ld];
-        bool hit = (h == 0.0);
-        if (!hit) {
-            double h21 = fabs(h);
-            if (h21 <= smlnum) hit = true;
-            else {
-                double h11 = H[(l - 1) + (int64_t)(l - 1) * ld], h22 = H[l + (int64_t)l * ld];
-                double tst = fabs(h11) + fabs(h22);
-                if (tst == 0.0) {
-                    if (l - 2 >= ilo) tst += fabs(H[(l - 1) + (int64_t)(l - 2) * ld]);
-                    if (l + 1 <= kbot) tst += fabs(H[(l + 1) + (int64_t)l * ld]);
-                }
-                if (h21 <= kU * tst) {
-                    double h12 = fabs(H[(l - 1) + (int64_t)l * ld]);
-                    double ab = fmax(h21, h12), ba = fmin(h21, h12);
-                    double d = fabs(h11 - h22);
-                    double aa = fmax(fabs(h22), d), bb = fmin(fabs(h22), d);
-                    double s = aa + ab;
-                    hit = ba * (ab / s) <= fmax(smlnum, kU * (bb * (aa / s)));
-                }
-            }
-        }
-        if (hit) {
+        if (H[l + (int64_t)(l - 1) * ld] == 0.0 || small_sub(H, ld, l, ilo, kbot, dfl)) {
             atomicMax(&S.ic[3], l);
             break;
         }
@@ -1944,14 +1909,14 @@ __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int i
     }
     identity_lds(S.Z, LDM, m, m);
     __syncthreads();
-    int info = qr_small(S, S.A, LDM, m, S.Z, LDM, m, smlnum, itmax, nsmall);
+    int info = qr_small(S, S.A, LDM, m, S.Z, LDM, m, dfl, itmax, nsmall);
     const long long t_schur = wall_clock64();
     long long t_defl = t_schur, t_rest = t_schur;
     int ns = 0, nd = m;
     double beta = 0.0;
     if (!small) {
         // spike = s * Z(0,:); bottom-up test; failures move to the top
-        ns = aed_deflate(S, S.A, LDM, m, S.Z, LDM, m, 0, s, info > 0 ? info : 0, smlnum);
+        ns = aed_deflate(S, S.A, LDM, m, S.Z, LDM, m, 0, s, info > 0 ? info : 0, dfl);
         t_defl = wall_clock64();
         nd = m - ns;
         if (tid == 0) {
@@ -2019,7 +1984,7 @@ __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int i
 
 // One workgroup per window of a chase round.
 __global__ void __launch_bounds__(NT) k_chase(double *H, int64_t ld, ChaseRound R, const double *sr,
-                                              const double *si, double smlnum, double *Ubuf, int64_t ustride)
+                                              const double *si, Defl dfl, double *Ubuf, int64_t ustride)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem &S = *reinterpret_cast<Smem *>(smem_raw);
@@ -2044,7 +2009,7 @@ __global__ void __launch_bounds__(NT) k_chase(double *H, int64_t ld, ChaseRound 
         int kl = k - a;
         bool z = false;
         if (kl >= 0 && kl + 1 < wa && S.A[(kl + 1) + kl * LDM] != 0.0)
-            z = small_sub(S.A, LDM, kl + 1, max(R.ktop - a, 0), min(R.kbot - a, wa - 1), smlnum);
+            z = small_sub(S.A, LDM, kl + 1, max(R.ktop - a, 0), min(R.kbot - a, wa - 1), dfl);
         S.vflag[i] = z ? 1 : 0;
     }
     __syncthreads();
@@ -2063,7 +2028,7 @@ __global__ void __launch_bounds__(NT) k_chase(double *H, int64_t ld, ChaseRound 
 
 // Corner deflation of a large AED window held in global memory.
 __global__ void __launch_bounds__(NT) k_corner_deflate(double *T, int64_t ldt, int nw, int wd, const double *V,
-                                                       int64_t ldv, double s, double smlnum, double *Ut,
+                                                       int64_t ldv, double s, Defl dfl, double *Ut,
                                                        IterStatus *st, int nforced)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -2082,7 +2047,7 @@ __global__ void __launch_bounds__(NT) k_corner_deflate(double *T, int64_t ldt, i
     for (int c = tid; c < wd; c += NT) S.Z[wd + c * LDM] = s * V[(int64_t)(c0 + c) * ldv];
     if (tid == 0) S.nswap = S.nrphase = 0;
     __syncthreads();
-    int nsc = aed_deflate(S, S.A, LDM, wd, S.Z, LDM, wd + 1, wd, 1.0, 0, smlnum, min(nforced, wd));
+    int nsc = aed_deflate(S, S.A, LDM, wd, S.Z, LDM, wd + 1, wd, 1.0, 0, dfl, min(nforced, wd));
     const int halted = S.ro.halt;
     __syncthreads();
     for (int it = tid; it < wd * wd; it += NT) {
@@ -2230,11 +2195,11 @@ __global__ void k_block_eigs(const double *T, int64_t ldt, int m, double *wr, do
 
 // Final pass, stage 1: standardizing rotation for every 2x2 block (computed on
 // a register copy of the block); blocks that need one are appended to a list.
-__global__ void k_fin_rot(const double *H, int64_t ld, int n, double *rc, double *rs, int *list, int *count,
-                          double *blk)
+__global__ void k_fin_rot(const double *H, int64_t ld, int n, int lo, double *rc, double *rs, int *list,
+                          int *count, double *blk)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    if (k < lo || k >= n) return; // rows above lo did not converge: no blocks there
     bool first = (k + 1 < n && H[(k + 1) + (int64_t)k * ld] != 0.0);
     bool second = (k > 0 && H[k + (int64_t)(k - 1) * ld] != 0.0);
     if (!first || second) return; // blocks never overlap in quasi-triangular T
@@ -2334,6 +2299,70 @@ __global__ void k_check_finite(const double *H, int64_t ld, int n, int *flag)
     }
 }
 
+// Frobenius norm of the Hessenberg part: one workgroup per column writes the
+// column's scaled sum of squares (scale = column max), then one workgroup
+// combines them.  Exact zeros are skipped; no overflow for finite input.
+__global__ void k_hess_fro_cols(const double *H, int64_t ld, int n, double *ws)
+{
+    __shared__ double red[256];
+    const int c = blockIdx.x;
+    const int rmax = min(c + 1, n - 1);
+    double mx = 0.0;
+    for (int r = threadIdx.x; r <= rmax; r += blockDim.x) mx = fmax(mx, fabs(H[r + (int64_t)c * ld]));
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    mx = red[0];
+    __syncthreads();
+    double ss = 0.0;
+    if (mx > 0.0)
+        for (int r = threadIdx.x; r <= rmax; r += blockDim.x) {
+            const double x = H[r + (int64_t)c * ld] / mx;
+            ss += x * x;
+        }
+    red[threadIdx.x] = ss;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ws[2 * c] = mx;
+        ws[2 * c + 1] = red[0];
+    }
+}
+
+__global__ void k_hess_fro_sum(const double *ws, int n, double *out)
+{
+    __shared__ double red[256];
+    double mx = 0.0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) mx = fmax(mx, ws[2 * c]);
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    mx = red[0];
+    __syncthreads();
+    double ss = 0.0;
+    if (mx > 0.0)
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            const double r = ws[2 * c] / mx;
+            ss += ws[2 * c + 1] * r * r;
+        }
+    red[threadIdx.x] = ss;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = mx * sqrt(red[0]);
+}
+
 __global__ void k_transpose_pad(const double *V, int64_t ldv, int K, double *Ut, int K16)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2365,41 +2394,41 @@ static hipError_t prep(const void *fn)
     return e;
 }
 
-hipError_t launch_iter(double *H, int64_t ld, int n, int ilo, int kbot, int nw, int nmin, double smlnum,
+hipError_t launch_iter(double *H, int64_t ld, int n, int ilo, int kbot, int nw, int nmin, Defl dfl,
                        int64_t itmax, double *Ut, IterStatus *st, hipStream_t s, int nsmall)
 {
     hipError_t e = prep((const void *)k_iter);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_iter, dim3(1), dim3(NT), smem_bytes(), s, H, ld, n, ilo, kbot, nw, nmin, smlnum,
+    hipLaunchKernelGGL(k_iter, dim3(1), dim3(NT), smem_bytes(), s, H, ld, n, ilo, kbot, nw, nmin, dfl,
                        itmax, Ut, st, nsmall);
     return hipGetLastError();
 }
 
-hipError_t launch_find_block(double *H, int64_t ld, int ilo, int kbot, double smlnum, IterStatus *st,
+hipError_t launch_find_block(double *H, int64_t ld, int ilo, int kbot, Defl dfl, IterStatus *st,
                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_find_block, dim3(1), dim3(NT), 0, s, H, ld, ilo, kbot, smlnum, st);
+    hipLaunchKernelGGL(k_find_block, dim3(1), dim3(NT), 0, s, H, ld, ilo, kbot, dfl, st);
     return hipGetLastError();
 }
 
 hipError_t launch_chase(double *H, int64_t ld, const ChaseRound &r, const double *sr, const double *si,
-                        double smlnum, double *Ubuf, int64_t ustride, hipStream_t s)
+                        Defl dfl, double *Ubuf, int64_t ustride, hipStream_t s)
 {
     hipError_t e = prep((const void *)k_chase);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_chase, dim3(r.nwin), dim3(NT), smem_bytes(), s, H, ld, r, sr, si, smlnum, Ubuf,
+    hipLaunchKernelGGL(k_chase, dim3(r.nwin), dim3(NT), smem_bytes(), s, H, ld, r, sr, si, dfl, Ubuf,
                        ustride);
     return hipGetLastError();
 }
 
 hipError_t launch_corner_deflate(double *T, int64_t ldt, int nw, int wd, const double *V, int64_t ldv,
-                                 double s, double smlnum, double *Ut, IterStatus *st, int nforced,
+                                 double s, Defl dfl, double *Ut, IterStatus *st, int nforced,
                                  hipStream_t stream)
 {
     hipError_t e = prep((const void *)k_corner_deflate);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_corner_deflate, dim3(1), dim3(NT), smem_bytes(), stream, T, ldt, nw, wd, V, ldv, s,
-                       smlnum, Ut, st, nforced);
+                       dfl, Ut, st, nforced);
     return hipGetLastError();
 }
 
@@ -2440,6 +2469,13 @@ hipError_t launch_zero_lower(double *H, int64_t ld, int n, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_hess_fro(const double *H, int64_t ld, int n, double *ws, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hess_fro_cols, dim3(n), dim3(256), 0, s, H, ld, n, ws);
+    hipLaunchKernelGGL(k_hess_fro_sum, dim3(1), dim3(256), 0, s, ws, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_transpose_pad(const double *V, int64_t ldv, int K, double *Ut, int K16, hipStream_t s)
 {
     int64_t tot = (int64_t)K16 * K16;
@@ -2448,8 +2484,9 @@ hipError_t launch_transpose_pad(const double *V, int64_t ldv, int K, double *Ut,
     return hipGetLastError();
 }
 
-// Final standardization pass; ws holds 8n doubles of scratch.
-hipError_t launch_finalize_ws(double *H, int64_t ld, int n, double *Q, double *wr, double *wi, double *ws,
+// Final standardization pass over the 2x2 blocks in rows lo..n-1 (lo > 0 when
+// the rows above did not converge); ws holds 8n doubles of scratch.
+hipError_t launch_finalize_ws(double *H, int64_t ld, int n, int lo, double *Q, double *wr, double *wi, double *ws,
                               hipStream_t s)
 {
     double *rc = ws, *rs = ws + n, *blk = ws + 2 * (int64_t)n;
@@ -2457,7 +2494,7 @@ hipError_t launch_finalize_ws(double *H, int64_t ld, int n, double *Q, double *w
     int *count = reinterpret_cast<int *>(ws + 7 * (int64_t)n);
     int nb = (n + 255) / 256;
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, count, 0);
-    hipLaunchKernelGGL(k_fin_rot, dim3(nb), dim3(256), 0, s, H, ld, n, rc, rs, list, count, blk);
+    hipLaunchKernelGGL(k_fin_rot, dim3(nb), dim3(256), 0, s, H, ld, n, lo, rc, rs, list, count, blk);
     hipLaunchKernelGGL(k_fin_rows, dim3(nb, 64), dim3(256), 0, s, H, ld, n, rc, rs, list, count);
     hipLaunchKernelGGL(k_fin_cols, dim3((2 * n + 255) / 256, 64), dim3(256), 0, s, H, ld, n, Q, rc, rs, list,
                        count, blk);
@@ -2592,8 +2629,8 @@ __global__ void __launch_bounds__(NT) k_batched(double *H, double *Q, const int6
         }
         identity_lds(S.Z, LDM, n, n);
         __syncthreads();
-        const double smlnum = DBL_MIN * ((double)n / kU);
-        int inf = qr_small(S, S.A, LDM, n, S.Z, LDM, n, smlnum, 0, 2);
+        const Defl dfl{DBL_MIN * ((double)n / kU), -1.0};
+        int inf = qr_small(S, S.A, LDM, n, S.Z, LDM, n, dfl, 0, 2);
         __syncthreads();
         for (int it = tid; it < n * n; it += NT) {
             int r = it % n, c = it / n;
@@ -2657,8 +2694,8 @@ __global__ void __launch_bounds__(NT) k_batched_global(double *H, double *Q, con
         }
         double *Z = Q ? Q + offs[b] : A; // without Q: no Z rows (nz = 0)
         __syncthreads();
-        const double smlnum = DBL_MIN * ((double)n / kU);
-        int inf = qr_small(S, A, n, n, Z, n, Q ? n : 0, smlnum, 0, 2);
+        const Defl dfl{DBL_MIN * ((double)n / kU), -1.0};
+        int inf = qr_small(S, A, n, n, Z, n, Q ? n : 0, dfl, 0, 2);
         __syncthreads();
         if (tid == 0) {
             batched_eigs(A, n, n, wr + eoff[b], wi + eoff[b]);

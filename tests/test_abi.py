@@ -42,7 +42,11 @@ def test_argument_validation_without_device_work(L):
     assert L.hqr_schur(p, None, 2, 2, p, None, None) == -6
     assert L.hqr_schur(p, None, 0, 1, p, p, None) == 0
     assert L.hqr_schur_batched(p, None, p, p, -1, p, p, p, p, None) == -5
-    assert L.hqr_eig_backward_batched(p, p, -2, 1, p, p, p, p, p, 1, None) == -3
+    assert L.hqr_eig_backward_batched(p, p, p, p, -2, p, p, p, p, p, 1, None) == -5
+    assert L.hqr_eig_backward_batched(p, p, None, p, 1, p, p, p, p, p, 1, None) == -3
+    assert L.hqr_eig_backward_batched(p, p, p, None, 1, p, p, p, p, p, 1, None) == -4
+    assert L.hqr_eig_backward_batched(p, p, p, p, 1, p, p, p, p, None, 1, None) == -10
+    assert L.hqr_eig_backward_batched(p, p, p, p, 0, p, p, p, p, p, 1, None) == 0
 
 
 def test_params_roundtrip_and_rejection(L):
@@ -55,9 +59,12 @@ def test_params_roundtrip_and_rejection(L):
     got = HqrParams()
     assert L.hqr_get_params(ctypes.byref(got)) == 0
     assert (got.ns, got.nw, got.nmin) == (64, 256, 60)
-    bad = HqrParams()
-    bad.defl_mode = 1  # only the LAPACK-style conditions are implemented
-    assert L.hqr_set_params(ctypes.byref(bad)) == -1
+    # deflation conditions: 0 LAPACK-style, 1 norm-stable, 2 fixed with a finite threshold >= 0
+    for mode, thold, rc in [(1, 0.0, 0), (2, 1e-12, 0), (2, 0.0, 0), (2, -1.0, -1), (2, float("inf"), -1),
+                            (2, float("nan"), -1), (3, 0.0, -1), (-1, 0.0, -1)]:
+        hp = HqrParams()
+        hp.defl_mode, hp.defl_thold = mode, thold
+        assert L.hqr_set_params(ctypes.byref(hp)) == rc, (mode, thold)
     assert L.hqr_set_params(ctypes.byref(old)) == 0
     assert L.hqr_set_params(None) == -1
 
