@@ -195,6 +195,8 @@ def batched_gaussian(sizes, seed: int = SEED):
     g = rng(seed)
     for i, n in enumerate(sizes):
         n = int(n)
+        if n == 0:
+            continue
         H = np.triu(g.standard_normal((n, n)))
         sub = g.standard_normal(n - 1)
         sub[np.abs(sub) < 1e-300] = 1.0

@@ -36,11 +36,11 @@ extern "C" {
 /* Algorithm parameters; a zero field means "automatic".
  *   ns      shifts per sweep (even)                         (Sec. 2.3)
  *   nw      AED window size                                  (Sec. 2.5)
- *   nmin    blocks of order <= nmin go to the small solver   (task 'small Schur', Sec. 3.1)
+ *   nmin    blocks of order <= nmin go to the small solver   (task 'small Schur', Sec. 3.2)
  *   nibble  skip the sweep when 100*nd > nibble*nw           (Sec. 2.5, repeated AED)
  *   kexsh   exceptional shifts after kexsh steps without deflation
  *   itmax   iteration limit (AED steps + sweeps)             (Sec. 2.1)
- *   window  bulge-chasing window order (<= 96)              (Sec. 3.1, 'push bulges')
+ *   window  bulge-chasing window order (<= 96)              (Sec. 3.2, 'push bulges')
  *   bulges_per_window  bulges in one window chain
  *   defl_mode  deflation conditions of Sec. 5.6: 0 = LAPACK-style (item 1:
  *              Ahues-Tisseur subdiagonal test, spike entries against u|t_kk|
@@ -49,7 +49,8 @@ extern "C" {
  *              input's Hessenberg part); 2 = fixed (item 3: against
  *              defl_thold, finite and >= 0).  Other values are rejected.
  *   streams    1 = everything on the caller's stream; 2 = updates outside the
- *              active block and to Q on a second stream (Sec. 3.3 priorities)
+ *              active block and to Q on a second stream (Sec. 3.4, ordering,
+ *              prioritization and lowest-priority tasks)
  *   small_shifts  shifts per sweep of the one-workgroup solver (2 = Francis
  *              double shift; 4..16 = chains of bulges shifted by the
  *              eigenvalues of the trailing block, Sec. 2.3)
@@ -88,7 +89,7 @@ int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double
                  const hqr_params *p);
 
 /* Batched form for many small independent problems (the paper's
- * small-block double-shift Francis solver of Sec. 3.1, `small Schur'), one
+ * small-block double-shift Francis solver of Sec. 3.2, `small Schur'), one
  * workgroup per matrix.  Matrix i has order n[i], stored packed column major at
  * H + offsets[i] with leading dimension n[i]; Q likewise (Q may be NULL;
  * otherwise it must hold Q0, e.g. identity, on entry, and receives Q0*Qhat).
@@ -110,6 +111,20 @@ int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double
  * use different queues.  Returns 0, or -k for a bad argument k. */
 int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int32_t batch,
                       double *wr, double *wi, const int64_t *eig_offsets, int32_t *info, void *stream);
+
+/* hqr_schur_batched for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the work queue in a fixed
+ * device array of the library (4 * (8 + 2^20) bytes, held on each GPU the
+ * library runs on until the process ends) instead of a buffer allocated on
+ * first use.  batch must not exceed 2^20 (1048576); larger batches return -5
+ * without doing any work.  The call allocates nothing, neither device nor
+ * host memory.  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on one GPU (on different streams, or from several threads) race
+ * and must not be issued; calls ordered on one stream are fine.  Arguments,
+ * layout, ownership and return codes as for hqr_schur_batched. */
+int hqr_schur_batched_noalloc(double *H, double *Q, const int64_t *offsets, const int32_t *n, int32_t batch,
+                              double *wr, double *wi, const int64_t *eig_offsets, int32_t *info, void *stream);
 
 /* Launch shape of the batched form's global-memory grid (orders > 96):
  * wg_per_cu workgroups per CU (1..8, default 2), and orders above wide_n

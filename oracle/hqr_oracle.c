@@ -343,7 +343,7 @@ static void eig2(double a, double b, double c, double d, double *r1, double *i1,
 }
 
 /* ------------------------------------------------------------------------- */
-/* Deflation tests (Sec. 5.3, item 1)                                          */
+/* Deflation tests (Sec. 5.6, item 1)                                          */
 /* ------------------------------------------------------------------------- */
 
 /* Vigilant test of the subdiagonal entry H[k,k-1] inside the block [lo,hi].

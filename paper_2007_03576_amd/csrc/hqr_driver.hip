@@ -2,17 +2,17 @@
 // deflation on one GPU (Myllykoski, ACM TOMS 48(1), 2021).
 //
 // The driver is the single-GPU form of the paper's event-driven main loop
-// (Sec. 3.2): the bottom unreduced block of the active segment is either
+// (Sec. 3.3 "Event-driven algorithm"): the bottom unreduced block of the active segment is either
 // handed to the small solver or gets an AED step; the AED outcome (number of
 // deflated eigenvalues and the shift candidates) is the one value the host
 // waits for in each iteration -- the analogue of acquiring the 'small AED'
 // return handle.  A repeated AED is chosen when many eigenvalues deflated
 // (Sec. 2.5); otherwise a multishift sweep is enqueued as rounds of
 // concurrent bulge-chasing windows ('push bulges') followed by the left and
-// right update products (Sec. 3.3).  Updates that cannot feed back into the
+// right update products (Sec. 3.4 "Bulge chasing").  Updates that cannot feed back into the
 // active block (columns right of it, rows above it, and Q) run on a second
 // stream at default priority, ordered after their inputs by events, so the
-// window chain and the AED -- the critical path of Sec. 3.3.1 -- never wait
+// window chain and the AED -- the critical path of Sec. 3.4.1 -- never wait
 // for them.
 #include "hqr_common.h"
 #include "../../include/hqr.h"
@@ -640,7 +640,8 @@ int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd
         return 0;
     }
     // Deflation check of the whole window by a chain of deflation windows of
-    // order <= 96 moving up from the bottom corner (Sec. 3.3, deflate tasks):
+    // order <= 96 moving up from the bottom corner (Sec. 3.5 "Parallel
+    // aggressive early deflation", chains of deflate tasks):
     // each window examines its unchecked candidates bottom-up, with the
     // failures of the windows below it (at its bottom) treated as failed,
     // and leaves all failures at its top; the next window ends at the
@@ -1166,6 +1167,60 @@ int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_
         }
         queue = qb.p;
     }
+    CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, queue, wg_per_cu, wide_n,
+                      (hipStream_t)stream));
+    return 0;
+}
+
+} // extern "C"
+
+// Work queue of hqr_schur_batched_noalloc: a fixed device array (each GPU
+// holds its own copy for the life of the process), so that entry point never
+// allocates.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns on each device.
+constexpr int64_t NOALLOC_MAX_BATCH = (int64_t)1 << 20;
+static __device__ __align__(256) int32_t scratch[QHDR + NOALLOC_MAX_BATCH];
+
+namespace {
+std::mutex g_scratch_mu;
+int32_t *g_scratch_ptr[16] = {nullptr};
+} // namespace
+
+extern "C" {
+
+int hqr_schur_batched_noalloc(double *H, double *Q, const int64_t *offsets, const int32_t *n, int32_t batch,
+                              double *wr, double *wi, const int64_t *eig_offsets, int32_t *info, void *stream)
+{
+    if (batch < 0 || (int64_t)batch > NOALLOC_MAX_BATCH) return -5;
+    if (batch == 0) return 0;
+    if (!H) return -1;
+    if (!offsets) return -3;
+    if (!n) return -4;
+    if (!wr) return -6;
+    if (!wi) return -7;
+    if (!eig_offsets) return -8;
+    if (!info) return -9;
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 16) return -1000;
+    int32_t *queue;
+    int wg_per_cu, wide_n;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void *ptr = nullptr;
+            CK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            g_scratch_ptr[dev] = static_cast<int32_t *>(ptr);
+        }
+        queue = g_scratch_ptr[dev];
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        wg_per_cu = g_batched_wg_per_cu;
+        wide_n = g_batched_wide_n;
+    }
+    // the sort kernel writes every queue head and position it uses, so the
+    // array needs no clearing between calls
     CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, queue, wg_per_cu, wide_n,
                       (hipStream_t)stream));
     return 0;

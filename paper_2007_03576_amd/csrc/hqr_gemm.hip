@@ -3,7 +3,7 @@
 // After a diagonal window has been processed (bulge chasing, AED, small Schur
 // solve) its accumulated orthogonal factor U (order K) must be applied to the
 // rest of the matrix: from the left to the rows of the window right of it,
-// from the right to the columns above it, and to Q (Sec. 2.3 and Sec. 3.1,
+// from the right to the columns above it, and to Q (Sec. 2.3 and Sec. 3.2.1,
 // 'left update' / 'right update' tasks).  Each workgroup owns a panel of
 // `tile` rows (right update) or columns (left update) of X, stages the whole
 // K-long panel in LDS, and overwrites it with the product, so the update is

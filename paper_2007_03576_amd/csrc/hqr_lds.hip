@@ -3,14 +3,15 @@
 // A workgroup of 256 threads keeps a matrix of order <= 96 and its accumulated
 // orthogonal factor in LDS and performs the sequential parts of the multishift
 // QR algorithm with AED (Myllykoski, ACM TOMS 48(1), 2021):
-//   * the small-block solver (task 'small Schur', Sec. 3.1): Francis double-shift
+//   * the small-block solver (task 'small Schur', Sec. 3.2 "Task types"): Francis double-shift
 //     iterations (Sec. 2.2), each sweep a bulge chased through the block;
-//   * the AED step for windows that fit LDS (task 'small AED', Sec. 3.1 and
+//   * the AED step for windows that fit LDS (task 'small AED', Sec. 3.2 and
 //     Sec. 2.5): Schur form of the window, bottom-up spike test with the
-//     LAPACK-style conditions of Sec. 5.3, reordering of failed candidates by
+//     conditions of Sec. 5.6 ("Comment regarding the deflation conditions and
+//     the accuracy"), reordering of failed candidates by
 //     Bai-Demmel swaps, spike removal and Hessenberg restoration;
 //   * the bulge-chasing windows of a multishift sweep (task 'push bulges',
-//     Sec. 3.1 and Sec. 2.3): a chain of tightly coupled bulges chased inside
+//     Sec. 3.2 and Sec. 2.3): a chain of tightly coupled bulges chased inside
 //     a diagonal window while the reflectors accumulate into U.
 // Every step of a chain moves all bulges by one row in three barrier-separated
 // phases: generate the reflectors (one thread per bulge), apply them from the
@@ -1434,8 +1435,8 @@ __device__ bool swap_xform(double *Tw, int ldt, int j, double smlnum, double *Go
 // Bottom-up deflation test of the candidates of the quasi-triangular T (order
 // nt) with spike entries sp_k = spscale * Z[sprow + k*ldz]; each failed
 // candidate moves up to the first free position of the undeflated region,
-// the remaining candidates shift down (Sec. 2.4, and the concurrent deflate
-// and reordering windows of the parallel AED, Sec. 3.3).
+// the remaining candidates shift down (Sec. 2.5, and the concurrent deflate
+// and reordering windows of Sec. 3.5 "Parallel aggressive early deflation").
 //
 // The moves are pipelined: a failed candidate starts to move as soon as it is
 // examined, and the next candidate (the block now below it) is examined as

@@ -113,6 +113,23 @@ def test_config1_gaussian_n4096(gpu):
     for idx in g.choice(n, 12, replace=False):
         res = hess_lu_residual(H, w[idx])
         assert res <= 100 * n * U * hn, (idx, w[idx], res)
+    # every eigenvalue against the oracle's on the same input (same ns, nw),
+    # matched one to one, within 1e-10 kappa_i ||H||_F
+    import time
+    t0 = time.perf_counter()
+    _, _, wo, oinfo, _ = oracle.schur(H, want_q=False, ns=64, nw=256)
+    _say(f"oracle n={n}: {time.perf_counter() - t0:.1f} s")
+    assert oinfo == 0
+    t0 = time.perf_counter()
+    lam, kap = checks.eig_condition(H)
+    _say(f"condition numbers: {time.perf_counter() - t0:.1f} s, max kappa {kap.max():.3e}")
+    r, c, d = checks.match(w, wo)
+    r2, c2, _ = checks.match(wo, lam)
+    kap_o = np.empty(n)
+    kap_o[r2] = kap[c2]
+    tol = 1e-10 * np.maximum(kap_o[c], 1.0) * hn
+    _say(f"matched {len(d)} eigenvalues: worst |dl|/tol {np.max(d / tol):.3e}")
+    assert len(d) == n and np.all(d <= tol)
 
 
 def nearest_both_ways(w, ref):
@@ -213,3 +230,60 @@ def test_config3_batched_sample(gpu):
         kap_o = np.empty(n)
         kap_o[r2] = kap[c2]
         assert np.all(d <= 1e-10 * np.maximum(kap_o[c], 1.0) * np.linalg.norm(H))
+
+
+def test_config4_differentiation_full_shape(gpu):
+    """The differentiation workload at its real shape: 512 Hessenberg matrices
+    of order 512 with well-separated prescribed spectra, forward through the
+    batched solver and backward through hqr_eig_backward_batched, in the
+    launch configuration the benchmark times.  Checked on a sample of the
+    batch: the oracle's gradient (4 matrices) and central differences with
+    h = 1e-6 along 20 seeded directions on the Hessenberg pattern (5 per
+    sampled matrix; the loss is a sum over matrices, so a direction supported
+    on one matrix sees only that matrix's eigenvalues)."""
+    import torch
+    import paper_2007_03576_amd as hq
+    count, n = 512, 512
+    _say(f"case config4 differentiation {count} x n={n}")
+    Hd, eigs = hi.prescribed_batch_device(count, n, seed=2020, device="cuda")
+    X = Hd.clone().requires_grad_(True)
+    lam = hq.eigvals(X)
+    loss = (torch.nn.functional.softplus(lam.real) + 0.1 * lam.abs() ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    G = X.grad.cpu().numpy()
+    Hn = Hd.cpu().numpy()
+    lam_n = lam.detach().cpu().numpy()
+    assert np.all(np.tril(G, -2) == 0.0)
+    # forward: every matrix's eigenvalues against its prescribed spectrum
+    worst = 0.0
+    for b in range(count):
+        d = nearest_both_ways(lam_n[b], np.asarray(eigs[b]))
+        worst = max(worst, d / np.linalg.norm(Hn[b]))
+    _say(f"forward: worst nearest distance / ||H||_F {worst:.3e}")
+    assert worst <= 1e-10
+
+    def loss_np(w):
+        return float(np.sum(np.logaddexp(0.0, w.real)) + 0.1 * np.sum(np.abs(w) ** 2))
+
+    g = np.random.default_rng(4)
+    sample = g.choice(count, 4, replace=False)
+    h = 1e-6
+    for b in sample:
+        H = Hn[b]
+        T, Q, w, info, _ = oracle.schur(H)
+        assert info == 0
+        gw = 1.0 / (1.0 + np.exp(-w.real)) + 0.2 * w
+        do = oracle.eig_backward(T, Q, w, gw)
+        err = np.abs(G[b] - do).max() / np.abs(do).max()
+        _say(f"matrix {b}: gradient rel err vs oracle {err:.2e}")
+        assert err <= 1e-8
+        for _ in range(5):
+            D = np.triu(g.standard_normal((n, n)), -1)
+            D /= np.linalg.norm(D)
+            lp = loss_np(oracle.schur(H + h * D, want_q=False)[2])
+            lm = loss_np(oracle.schur(H - h * D, want_q=False)[2])
+            fd = (lp - lm) / (2 * h)
+            an = float(np.sum(G[b] * D))
+            _say(f"  direction: fd {fd:.9e} analytic {an:.9e}")
+            assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (b, fd, an)
