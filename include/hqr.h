@@ -35,7 +35,7 @@ extern "C" {
 
 /* Algorithm parameters; a zero field means "automatic".
  *   ns      shifts per sweep (even)                         (Sec. 2.3)
- *   nw      AED window size                                  (Sec. 2.5)
+ *   nw      AED window size, at most 1024                    (Sec. 2.5)
  *   nmin    blocks of order <= nmin go to the small solver   (task 'small Schur', Sec. 3.2)
  *   nibble  skip the sweep when 100*nd > nibble*nw           (Sec. 2.5, repeated AED)
  *   kexsh   exceptional shifts after kexsh steps without deflation
@@ -83,6 +83,21 @@ int hqr_get_params(hqr_params *p);
  * Blocks the host until done: the driver reads back one small status record
  * per iteration (the deflation count and the shifts of each AED step). */
 int hqr_schur(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi, void *stream);
+
+/* Reduction of a dense square matrix to upper Hessenberg form, the phase
+ * before the Schur reduction (Sec. 1: dense -> Hessenberg -> Schur form;
+ * Sec. 5.5 "Comment regarding the Hessenberg reduction phase"):
+ * A (n x n, leading dimension ld >= max(1,n), column major, device) is
+ * overwritten by H = Q_h^T A Q_h with exact zeros below the subdiagonal;
+ * Q (device, same ld; may be NULL) is overwritten by Q Q_h (pass the identity
+ * to obtain Q_h).  Q_h e_1 = e_1 and the reflectors follow the convention
+ * beta = -sign(alpha) ||x||, so H and Q_h are those of LAPACK's dgehrd/dorghr
+ * up to rounding.  Blocked Householder reduction: per panel of 32 columns a
+ * one-workgroup column kernel and a many-workgroup matrix-vector product,
+ * then FP64-MFMA updates of the rest.  Blocks the host until done.
+ * Returns 0, -k for a bad argument k (non-finite entries of A count as
+ * argument 1), or -1000-e for a HIP error e. */
+int hqr_hessenberg(double *A, double *Q, int64_t n, int64_t ld, void *stream);
 
 /* Same as hqr_schur with explicit parameters for this call only (p may be NULL). */
 int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi, void *stream,

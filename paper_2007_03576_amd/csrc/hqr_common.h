@@ -15,6 +15,7 @@ constexpr int WMAX = 96;           // largest bulge-chasing window
 constexpr int GMAX = 16;           // most bulges chased in one window
 constexpr int MAXWIN = 16;         // most windows in one chase round
 constexpr int MAXCAND = 1024;      // candidate eigenvalues returned by one AED step
+constexpr int MAX_UPDATE_K = 1024; // largest factor order k_update stages (16 x (1024 + 4) doubles of LDS)
 
 // Deflation conditions of the solver (Sec. 5.6, "Comment regarding the
 // deflation conditions and the accuracy").  thr < 0: LAPACK-style conditions
@@ -126,6 +127,7 @@ hipError_t launch_block_eigs(const double *T, int64_t ldt, int m, double *wr, do
 hipError_t launch_finalize_ws(double *H, int64_t ld, int n, int lo, double *Q, double *wr, double *wi, double *ws,
                               hipStream_t s);
 hipError_t launch_check_finite(const double *H, int64_t ld, int n, int *flag, hipStream_t s);
+hipError_t launch_check_finite_full(const double *A, int64_t ld, int n, int *flag, hipStream_t s);
 // Frobenius norm of the Hessenberg part of H (n x n) into *out (device), for
 // the norm-stable deflation threshold; ws holds n doubles of scratch.
 hipError_t launch_hess_fro(const double *H, int64_t ld, int n, double *ws, double *out, hipStream_t s);
@@ -149,6 +151,22 @@ struct BwdDesc {
 hipError_t launch_eig_backward_chunk(const double *T, const double *Q, const BwdDesc *D, int nb, int nmax,
                                      const double *wr, const double *wi, const double *gwr, const double *gwi,
                                      double *dH, int hess_mask, double *ws, hipStream_t s);
+
+// ---- blocked Householder Hessenberg reduction (hqr_hess.hip) ----
+constexpr int NBH = 32; // panel width
+// Doubles of workspace hess_reduce / restore_blocked need for order m, nr
+// extra columns and nz rows of Z.
+size_t hess_ws_doubles(int m, int nr, int nz);
+// A (m x m, lda) <- Q^T A Q upper Hessenberg; the nr columns stored right of A
+// (A + m*lda ...) <- Q^T (them); Z (nz x m, ldz; may be NULL) <- Z Q.
+hipError_t hess_reduce(double *A, int64_t lda, int m, int nr, double *Z, int64_t ldz, int nz, double *ws,
+                       hipStream_t s);
+// Hessenberg restoration of a large AED window: spike reflector from s * V(0, 0:ns),
+// applied to T rows/columns 0..ns-1 and V columns, then hess_reduce of
+// T(0:ns, 0:ns) with the window columns ns..nw-1 and V (nv rows); the new
+// subdiagonal entry left of the window (beta) goes to *beta_dev.
+hipError_t restore_blocked(double *T, int64_t ldt, int nw, int ns, double *Vw, int64_t ldv, int nv, double s,
+                           double *ws, double *beta_dev, hipStream_t st);
 
 // ---- launchers (hqr_gemm.hip) ----
 hipError_t launch_updates(const UpdBatch &b, hipStream_t s);

@@ -108,6 +108,10 @@ hipError_t g_err = hipSuccess;
         }                                                                                                      \
     } while (0)
 
+// Undeflated orders of a large AED window from which the Hessenberg
+// restoration runs as the blocked many-CU reduction instead of one workgroup.
+constexpr int RESTORE_BLOCKED_MIN = 128;
+
 struct Workspace {
     int dev = -1;
     hipStream_t lo = nullptr;          // deferred-update stream
@@ -127,6 +131,8 @@ struct Workspace {
     std::vector<hipEvent_t> wU_ev;     // recorded on lo after the last deferred use of wU
     std::vector<char> wU_pending;
     double *vbuf = nullptr;
+    double *hws = nullptr;             // blocked Hessenberg reduction workspace
+    size_t hws_n = 0;
     int *flag = nullptr;
     hipEvent_t ev_pool[64];
     int ev_next = 0;
@@ -134,6 +140,8 @@ struct Workspace {
 };
 
 Workspace g_ws[16];
+// Calls on one device run one at a time: they share its workspace.
+std::mutex g_ws_mu[16];
 
 // ---- optional kernel-class timing with HIP events (measurement tools) ----
 constexpr int NCLASS = 5; // 0 LDS iteration, 1 chase windows, 2 update products, 3 large-AED kernels, 4 other
@@ -680,7 +688,23 @@ int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd
         double beta = 0.0;
         if (ns > 1 && s != 0.0) {
             int pidr = prof_begin(3, C.hi);
-            CK(launch_restore(T, w, w, ns, Vw, w, w, s, W.vbuf, W.st_dev, C.hi));
+            if (ns >= RESTORE_BLOCKED_MIN) {
+                // many-CU blocked reduction (panels, GEMV, FP64-MFMA updates)
+                const size_t need = hess_ws_doubles(ns, w - ns, w);
+                if (W.hws_n < need) {
+                    if (W.hws) {
+                        CK(hipStreamSynchronize(C.hi));
+                        CK(hipFree(W.hws));
+                    }
+                    W.hws = nullptr;
+                    W.hws_n = 0;
+                    CK(hipMalloc(&W.hws, sizeof(double) * need));
+                    W.hws_n = need;
+                }
+                CK(restore_blocked(T, w, w, ns, Vw, w, w, s, W.hws, &W.st_dev->beta, C.hi));
+            } else {
+                CK(launch_restore(T, w, w, ns, Vw, w, w, s, W.vbuf, W.st_dev, C.hi));
+            }
             prof_end(pidr, C.hi, 10.0 / 3.0 * (double)ns * ns * ns + 4.0 * (double)w * ns * ns, 0.0);
             CK(hipMemcpyAsync(&W.st_host->beta, &W.st_dev->beta, sizeof(double), hipMemcpyDeviceToHost, C.hi));
         } else if (ns >= 1) {
@@ -937,6 +961,7 @@ Params resolve(const hqr_params *pp, int n)
     P.aed_nw = p.aed_nw > 0 ? std::max(4, std::min(p.aed_nw, MMAX)) : 0;
     P.aed_nmin = p.aed_nmin > 0 ? std::max(12, std::min(p.aed_nmin, MMAX)) : 0;
     if (P.nw < 2) P.nw = 2;
+    P.nw = std::min(P.nw, MAX_UPDATE_K); // the window factor is applied by k_update
     P.defl_mode = p.defl_mode;
     P.defl_thold = p.defl_thold;
     return P;
@@ -979,6 +1004,7 @@ int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double
     CK(hipGetDevice(&dev));
     if (dev < 0 || dev >= 16) return -1000;
     Workspace &W = g_ws[dev];
+    std::lock_guard<std::mutex> lk(g_ws_mu[dev]);
     int e = ensure_ws(W, dev);
     if (e) return e;
     Params P = resolve(pp, (int)n);
@@ -1038,6 +1064,41 @@ int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double
 int hqr_schur(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi, void *stream)
 {
     return hqr_schur_ex(H, Q, n, ld, wr, wi, stream, nullptr);
+}
+
+int hqr_hessenberg(double *A, double *Q, int64_t n, int64_t ld, void *stream)
+{
+    if (n < 0) return -3;
+    if (n == 0) return 0;
+    if (!A) return -1;
+    if (ld < std::max<int64_t>(1, n)) return -4;
+    if (n > (int64_t)INT32_MAX / 2) return -3;
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 16) return -1000;
+    Workspace &W = g_ws[dev];
+    std::lock_guard<std::mutex> lk(g_ws_mu[dev]);
+    int e = ensure_ws(W, dev);
+    if (e) return e;
+    hipStream_t st = (hipStream_t)stream;
+    // argument check on the device: non-finite entries
+    CK(hipMemsetAsync(W.flag, 0, sizeof(int), st));
+    CK(launch_check_finite_full(A, ld, (int)n, W.flag, st));
+    CK(hipMemcpyAsync(&W.st_host->pad, W.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (W.st_host->pad) return -1;
+    const size_t need = hess_ws_doubles((int)n, 0, Q ? (int)n : 0);
+    if (W.hws_n < need) {
+        if (W.hws) CK(hipFree(W.hws)); // the stream was synchronized above
+        W.hws = nullptr;
+        W.hws_n = 0;
+        CK(hipMalloc(&W.hws, sizeof(double) * need));
+        W.hws_n = need;
+    }
+    CK(hess_reduce(A, ld, (int)n, 0, Q, ld, Q ? (int)n : 0, W.hws, st));
+    CK(launch_zero_lower(A, ld, (int)n, st));
+    CK(hipStreamSynchronize(st)); // the workspace is reused by the next call
+    return 0;
 }
 
 int hqr_last_stats(int64_t *stats, int len)
@@ -1103,6 +1164,7 @@ int hqr_finalize(void)
         hipFree(W.ubuf);
         hipFree(W.fin);
         hipFree(W.vbuf);
+        hipFree(W.hws);
         hipFree(W.flag);
         for (auto e : W.wU_ev) hipEventDestroy(e);
         for (size_t d = 0; d < W.wT.size(); ++d) {

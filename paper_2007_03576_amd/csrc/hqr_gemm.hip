@@ -19,11 +19,13 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int UPD_THREADS = 256;
 
+// Panel rows/columns per workgroup: 64, fewer when the K16 x (tile + 4) panel
+// would not fit the 160 KB of LDS (K16 <= 1024, see MAX_UPDATE_K).
 int update_tile(int K16, int side)
 {
     (void)side;
     int t = 64;
-    while (t > 16 && (size_t)t * (size_t)(K16 + 4) * 8 > 132 * 1024) t /= 2;
+    while (t > 16 && (size_t)K16 * (size_t)(t + 4) * 8 > 160 * 1024) t /= 2;
     return t;
 }
 
@@ -60,33 +62,44 @@ __global__ void __launch_bounds__(UPD_THREADS) k_update(UpdBatch B)
         }
     }
     __syncthreads();
+    // work items: (panel tile of 16 rows/columns, group of up to SG output
+    // strips of 16); with K <= 96 the four waves take one panel tile each and
+    // every strip, so they carry equal MFMA work
+    constexpr int SG = 6;
     const int lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
     const int ntj = K16 / 16;
-    const int nta = TA / 16;
+    const int nta = (cnt + 15) / 16;
+    const int ngrp = (ntj + SG - 1) / SG;
     const double *Ut = J.Ut;
-    for (int jt = wave; jt < ntj; jt += UPD_THREADS / 64) {
-        dbl4 acc[4];
-        for (int q = 0; q < 4; ++q) acc[q] = (dbl4){0.0, 0.0, 0.0, 0.0};
-        const double *ua = Ut + (jt * 16 + l16) + (int64_t)lq * K16;
-#pragma unroll 4
+    for (int item = wave; item < nta * ngrp; item += UPD_THREADS / 64) {
+        const int at = item % nta, j0 = (item / nta) * SG;
+        const int nj = min(SG, ntj - j0);
+        dbl4 acc[SG];
+#pragma unroll
+        for (int q = 0; q < SG; ++q) acc[q] = (dbl4){0.0, 0.0, 0.0, 0.0};
+        const double *ua = Ut + j0 * 16 + l16 + (int64_t)lq * K16;
+        const double *pb = Pt + lq * TAP + at * 16 + l16;
+#pragma unroll 2
         for (int k0 = 0; k0 < K16; k0 += 4) {
-            double af = ua[(int64_t)k0 * K16];
-            const double *pb = Pt + (k0 + lq) * TAP + l16;
-            if (nta > 0) acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, pb[0], acc[0], 0, 0, 0);
-            if (nta > 1) acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, pb[16], acc[1], 0, 0, 0);
-            if (nta > 2) acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, pb[32], acc[2], 0, 0, 0);
-            if (nta > 3) acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, pb[48], acc[3], 0, 0, 0);
+            const double bf = pb[k0 * TAP];
+            const double *uk = ua + (int64_t)k0 * K16;
+#pragma unroll
+            for (int q = 0; q < SG; ++q)
+                if (q < nj) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(uk[q * 16], bf, acc[q], 0, 0, 0);
         }
         // D[i][n]: i = lq + 4r (row of U^T, i.e. output index j), n = l16 (panel index a);
         // lane layout of the f64 16x16x4 result checked on gfx950
-        for (int at = 0; at < nta; ++at) {
-            int a = at * 16 + l16;
-            if (a >= cnt) continue;
+        const int a = at * 16 + l16;
+        if (a >= cnt) continue;
+#pragma unroll
+        for (int q = 0; q < SG; ++q) {
+            if (q >= nj) continue;
+#pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int jj = jt * 16 + lq + 4 * r;
+                const int jj = (j0 + q) * 16 + lq + 4 * r;
                 if (jj >= K) continue;
-                double v = acc[at][r];
+                const double v = acc[q][r];
                 if (J.side == 0)
                     X[(int64_t)(a_base + a) + (int64_t)jj * ldx] = v;
                 else

@@ -1,0 +1,441 @@
+// Blocked Householder reduction to upper Hessenberg form on gfx950 (many CUs).
+//
+// Two users in libhqr:
+//   * the phase before the Schur reduction (Sec. 1: dense matrix -> Hessenberg
+//     form -> Schur form; Sec. 5.5 "Comment regarding the Hessenberg reduction
+//     phase"): A <- Q_h^T A Q_h, Q <- Q Q_h (hqr_hessenberg);
+//   * the Hessenberg restoration of a large AED window (Sec. 2.5, third
+//     sub-step): after the spike has been reduced to beta e_1 by one
+//     reflector, the undeflated leading block of the window's Schur form is
+//     reduced back to Hessenberg form, its transformation also applied from
+//     the left to the window columns right of the block and from the right
+//     to the window's orthogonal factor.
+//
+// Panels of NBH columns.  With A0 the matrix at the start of a panel, Q_p =
+// I - V T V^T the product of the panel's reflectors and Y = A0 V T:
+//   * column c = k + j of the result is Q_j^T (A0 - Y_j V_j^T) e_c (only the
+//     panel's first j reflectors act on it); its reflector extends V and T,
+//     and y_j = A0 v_j is a matrix-vector product over all rows (k_hh_gemv,
+//     many workgroups, partial sums per column chunk) that the next column's
+//     kernel folds into Y (k_hh_col, one workgroup of 1024 threads);
+//   * after the panel: A <- Q_p^T (A0 - Y V^T) on the columns right of the
+//     panel (extra columns R included in the left product) and Z <- Z Q_p,
+//     as FP64-MFMA matrix products (k_hh_gemm).
+// Everything stays on the device: no host synchronization inside.
+#include "hqr_common.h"
+#include <algorithm>
+#include <cfloat>
+
+namespace hqr {
+
+typedef double dbl4h __attribute__((ext_vector_type(4)));
+
+constexpr int HT = 1024; // threads of the panel-column kernel
+
+// Sum of `cnt` per-thread partial values (cnt <= NBH) over the workgroup;
+// every thread receives all sums in out[] (LDS scratch red: 16 x NBH).
+__device__ inline void hh_multi_sum(const double (&vals)[NBH], int cnt, double *red, double *out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads(); // earlier readers of red are done
+#pragma unroll
+    for (int i = 0; i < NBH; ++i) {
+        if (i < cnt) {
+            double v = vals[i];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) red[wave * NBH + i] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += red[w * NBH + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+__device__ inline double hh_sum(double v, double *red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[w];
+    return t;
+}
+
+__device__ inline double hh_max(double v, double *red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t = fmax(t, red[w]);
+    return t;
+}
+
+// Panel step j (column c = k + j) of a matrix of order m, leading dimension
+// lda.  When j > 0 first completes Y(:, j-1) = tau_{j-1} (sum of the GEMV
+// partials - Y(:, :j-1) w_{j-1}).  When form != 0 then forms column c,
+// writes its final values and its reflector (V(:, j), tau_j, T(:, j),
+// w_j = V(:, :j)^T v_j).  V, Y: m x NBH (ld m); T: NBH x NBH; W: NBH x NBH
+// (column j = w_j); tau: NBH; part: nchunk x m.
+__global__ void __launch_bounds__(HT) k_hh_col(double *A, int64_t lda, int m, int k, int j, int form,
+                                               double *V, double *Y, double *Tm, double *W, double *tau,
+                                               const double *part, int nchunk)
+{
+    __shared__ double red[16 * NBH];
+    __shared__ double sv[NBH];
+    __shared__ double sv2[NBH];
+    const int tid = threadIdx.x;
+    const int64_t ldm = m;
+    if (j > 0) {
+        const int jp = j - 1;
+        const double tp = tau[jp];
+        for (int r = tid; r < m; r += HT) {
+            double y = 0.0;
+            for (int q = 0; q < nchunk; ++q) y += part[(int64_t)q * m + r];
+            double s = 0.0;
+            for (int i = 0; i < jp; ++i) s += Y[r + i * ldm] * W[i + jp * NBH];
+            Y[r + jp * ldm] = tp * (y - s);
+        }
+        __syncthreads();
+    }
+    if (!form) return;
+    const int c = k + j;
+    // x = A0(:, c) - Y(:, :j) V(c, :j)^T ; kept in V(:, j) as scratch until the reflector is known
+    if (tid < j) sv[tid] = V[c + tid * ldm];
+    __syncthreads();
+    double *x = V + (int64_t)j * ldm;
+    double loc[NBH];
+#pragma unroll
+    for (int i = 0; i < NBH; ++i) loc[i] = 0.0;
+    for (int r = tid; r < m; r += HT) {
+        double v = A[r + (int64_t)c * lda];
+        for (int i = 0; i < j; ++i) v -= Y[r + i * ldm] * sv[i];
+        x[r] = v;
+        if (r >= k + 1) {
+#pragma unroll
+            for (int i = 0; i < NBH; ++i)
+                if (i < j) loc[i] += V[r + i * ldm] * v;
+        }
+    }
+    // x(k+1:) <- Q_{j-1}^T x = x - V T^T (V^T x)
+    hh_multi_sum(loc, j, red, sv);
+    if (tid == 0)
+        for (int i = 0; i < j; ++i) {
+            double t = 0.0;
+            for (int l = 0; l <= i; ++l) t += Tm[l + i * NBH] * sv[l]; // (T^T s)_i = sum_l T(l, i) s_l
+            sv2[i] = t;
+        }
+    __syncthreads();
+    double amax = 0.0;
+    for (int r = tid; r < m; r += HT) {
+        double v = x[r];
+        if (r >= k + 1)
+            for (int i = 0; i < j; ++i) v -= V[r + i * ldm] * sv2[i];
+        x[r] = v;
+        if (r <= c) A[r + (int64_t)c * lda] = v; // final rows 0..c of column c
+        if (r >= c + 2) amax = fmax(amax, fabs(v));
+    }
+    amax = hh_max(amax, red);
+    const double x0 = x[c + 1]; // read before any thread overwrites x below
+    double ss = 0.0;
+    if (amax > 0.0)
+        for (int r = c + 2 + tid; r < m; r += HT) {
+            const double t = x[r] / amax;
+            ss += t * t;
+        }
+    ss = hh_sum(ss, red);
+    double tj = 0.0, beta = x0, scal = 0.0;
+    if (amax > 0.0) {
+        const double nrm = hypot(x0, amax * sqrt(ss));
+        beta = (x0 >= 0.0) ? -nrm : nrm;
+        tj = (beta - x0) / beta;
+        scal = 1.0 / (x0 - beta);
+    }
+    // v_j (unit at c+1, zero above), the reduced column, w_j = V(:, :j)^T v_j
+#pragma unroll
+    for (int i = 0; i < NBH; ++i) loc[i] = 0.0;
+    for (int r = tid; r < m; r += HT) {
+        double v;
+        if (r <= c) v = 0.0;
+        else if (r == c + 1) v = 1.0;
+        else v = (tj != 0.0) ? x[r] * scal : 0.0;
+        x[r] = v;
+        if (r == c + 1) A[r + (int64_t)c * lda] = beta;
+        else if (r > c + 1) A[r + (int64_t)c * lda] = 0.0;
+        if (r >= c + 1) {
+#pragma unroll
+            for (int i = 0; i < NBH; ++i)
+                if (i < j) loc[i] += V[r + i * ldm] * v;
+        }
+    }
+    hh_multi_sum(loc, j, red, sv);
+    if (tid == 0) {
+        for (int i = 0; i < j; ++i) W[i + j * NBH] = sv[i];
+        // T(:j, j) = -tau_j T(:j, :j) w_j
+        for (int i = 0; i < j; ++i) {
+            double t = 0.0;
+            for (int l = i; l < j; ++l) t += Tm[i + l * NBH] * sv[l];
+            Tm[i + j * NBH] = -tj * t;
+        }
+        Tm[j + j * NBH] = tj;
+        for (int i = j + 1; i < NBH; ++i) Tm[i + j * NBH] = 0.0;
+        tau[j] = tj;
+    }
+}
+
+// Partial sums of y = A(:, c+1:m) v(c+1:m) for column chunks: grid (row
+// blocks of 256, nchunk); part[q * m + r].
+__global__ void __launch_bounds__(256) k_hh_gemv(const double *A, int64_t lda, int m, int c, const double *v,
+                                                 double *part, int nchunk)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int q = blockIdx.y;
+    const int c0 = c + 1, ncol = m - c0;
+    const int per = (ncol + nchunk - 1) / nchunk;
+    const int lo = c0 + q * per, hi = min(m, lo + per);
+    if (r >= m) return;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int col = lo;
+    for (; col + 3 < hi; col += 4) {
+        s0 += A[r + (int64_t)col * lda] * v[col];
+        s1 += A[r + (int64_t)(col + 1) * lda] * v[col + 1];
+        s2 += A[r + (int64_t)(col + 2) * lda] * v[col + 2];
+        s3 += A[r + (int64_t)(col + 3) * lda] * v[col + 3];
+    }
+    for (; col < hi; ++col) s0 += A[r + (int64_t)col * lda] * v[col];
+    part[(int64_t)q * m + r] = (s0 + s1) + (s2 + s3);
+}
+
+// C(0:mm, 0:nn) = beta C + alpha op(A) op(B), inner dimension kk, FP64 MFMA,
+// 64 x 64 tiles; opA/opB 0 = as stored (column major), 1 = transposed.
+constexpr int HGT = 64, HGK = 16, HGP = 4;
+__global__ void __launch_bounds__(256) k_hh_gemm(int mm, int nn, int kk, double alpha, const double *A, int64_t lda,
+                                                 int opA, const double *B, int64_t ldb, int opB, double beta,
+                                                 double *C, int64_t ldc)
+{
+    __shared__ double As[HGK][HGT + HGP];
+    __shared__ double Bs[HGK][HGT + HGP];
+    const int m0 = blockIdx.x * HGT, n0 = blockIdx.y * HGT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int l16 = lane & 15, lq = lane >> 4;
+    dbl4h acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = (dbl4h){0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < kk; k0 += HGK) {
+        for (int it = tid; it < HGT * HGK; it += 256) {
+            int mi, ki;
+            if (opA == 0) {
+                mi = it % HGT;
+                ki = it / HGT;
+            } else {
+                ki = it % HGK;
+                mi = it / HGK;
+            }
+            const int gm = m0 + mi, gk = k0 + ki;
+            double v = 0.0;
+            if (gm < mm && gk < kk) v = (opA == 0) ? A[gm + (int64_t)gk * lda] : A[gk + (int64_t)gm * lda];
+            As[ki][mi] = v;
+            int nj, kj;
+            if (opB == 0) {
+                kj = it % HGK;
+                nj = it / HGK;
+            } else {
+                nj = it % HGT;
+                kj = it / HGT;
+            }
+            const int gn = n0 + nj, gk2 = k0 + kj;
+            double w = 0.0;
+            if (gn < nn && gk2 < kk) w = (opB == 0) ? B[gk2 + (int64_t)gn * ldb] : B[gn + (int64_t)gk2 * ldb];
+            Bs[kj][nj] = w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < HGK; ks += 4) {
+            double af[2], bf[2];
+            for (int a = 0; a < 2; ++a) af[a] = As[ks + lq][wm + a * 16 + l16];
+            for (int b = 0; b < 2; ++b) bf[b] = Bs[ks + lq][wn + b * 16 + l16];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // lane holds D[lq + 4r][l16] of each 16 x 16 block
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + a * 16 + lq + 4 * r;
+                const int gn = n0 + wn + b * 16 + l16;
+                if (gm < mm && gn < nn) {
+                    double *p = C + gm + (int64_t)gn * ldc;
+                    *p = (beta == 0.0 ? 0.0 : beta * *p) + alpha * acc[a][b][r];
+                }
+            }
+}
+
+static hipError_t hh_gemm(int mm, int nn, int kk, double alpha, const double *A, int64_t lda, int opA,
+                          const double *B, int64_t ldb, int opB, double beta, double *C, int64_t ldc, hipStream_t s)
+{
+    if (mm <= 0 || nn <= 0) return hipSuccess;
+    dim3 grid((mm + HGT - 1) / HGT, (nn + HGT - 1) / HGT);
+    hipLaunchKernelGGL(k_hh_gemm, grid, dim3(256), 0, s, mm, nn, kk, alpha, A, lda, opA, B, ldb, opB, beta, C, ldc);
+    return hipGetLastError();
+}
+
+// Spike reflector of a large AED window (Sec. 2.5): g = s * Z(0, 0:m) (row 0
+// of the window's factor), reflector P = I - tau u u^T with P g = beta e_1;
+// u, tau and beta go to hv (m + 2 doubles: u, tau, beta).  One workgroup.
+__global__ void __launch_bounds__(HT) k_hh_spike(const double *Z, int64_t ldz, int m, double s, double *hv)
+{
+    __shared__ double red[16];
+    const int tid = threadIdx.x;
+    double amax = 0.0;
+    for (int i = 1 + tid; i < m; i += HT) amax = fmax(amax, fabs(s * Z[(int64_t)i * ldz]));
+    amax = hh_max(amax, red);
+    double ss = 0.0;
+    if (amax > 0.0)
+        for (int i = 1 + tid; i < m; i += HT) {
+            const double t = s * Z[(int64_t)i * ldz] / amax;
+            ss += t * t;
+        }
+    ss = hh_sum(ss, red);
+    const double x0 = s * Z[0];
+    double tj = 0.0, beta = x0, scal = 0.0;
+    if (amax > 0.0) {
+        const double nrm = hypot(x0, amax * sqrt(ss));
+        beta = (x0 >= 0.0) ? -nrm : nrm;
+        tj = (beta - x0) / beta;
+        scal = 1.0 / (x0 - beta);
+    }
+    for (int i = tid; i < m; i += HT) hv[i] = (i == 0) ? 1.0 : ((tj != 0.0) ? s * Z[(int64_t)i * ldz] * scal : 0.0);
+    if (tid == 0) {
+        hv[m] = tj;
+        hv[m + 1] = beta;
+    }
+}
+
+// One reflector u (length m, from hv) applied from the left to columns
+// 0..ncol-1 of M (rows 0..m-1): one thread per column.
+__global__ void k_hh_refl_left(double *M, int64_t ldm, int m, int ncol, const double *hv)
+{
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= ncol) return;
+    const double t = hv[m];
+    if (t == 0.0) return;
+    double *x = M + (int64_t)col * ldm;
+    double d = 0.0;
+    for (int i = 0; i < m; ++i) d += hv[i] * x[i];
+    d *= t;
+    for (int i = 0; i < m; ++i) x[i] -= d * hv[i];
+}
+
+// The same reflector from the right to rows 0..nrow-1 of M (columns 0..m-1):
+// one thread per row.
+__global__ void k_hh_refl_right(double *M, int64_t ldm, int m, int nrow, const double *hv)
+{
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= nrow) return;
+    const double t = hv[m];
+    if (t == 0.0) return;
+    double d = 0.0;
+    for (int i = 0; i < m; ++i) d += M[row + (int64_t)i * ldm] * hv[i];
+    d *= t;
+    for (int i = 0; i < m; ++i) M[row + (int64_t)i * ldm] -= d * hv[i];
+}
+
+size_t hess_ws_doubles(int m, int nr, int nz)
+{
+    const size_t mm = (size_t)std::max(m, 1);
+    const size_t nchunk = 64;
+    // V, Y, VT (m x NBH), T, W (NBH x NBH), tau (NBH), partials (nchunk x m),
+    // WL (NBH x (m + nr)), ZW, ZT (nz x NBH), spike vector (m + 2)
+    return 3 * mm * NBH + 2 * (size_t)NBH * NBH + NBH + nchunk * mm + (size_t)NBH * (mm + nr) +
+           2 * (size_t)std::max(nz, 1) * NBH + mm + 2;
+}
+
+hipError_t hess_reduce(double *A, int64_t lda, int m, int nr, double *Z, int64_t ldz, int nz, double *ws,
+                       hipStream_t s)
+{
+    if (m < 3) return hipSuccess;
+    const size_t mm = (size_t)m;
+    double *V = ws, *Y = V + mm * NBH, *VT = Y + mm * NBH;
+    double *Tm = VT + mm * NBH, *W = Tm + NBH * NBH, *tau = W + NBH * NBH;
+    double *part = tau + NBH;
+    // chunks of columns for the GEMV partials: about 1024 workgroups in all
+    const int rblk = (m + 255) / 256;
+    const int nchunk_max = 64;
+    double *WL = part + (size_t)nchunk_max * mm;
+    double *ZW = WL + (size_t)NBH * (mm + nr);
+    double *ZT = ZW + (size_t)std::max(nz, 1) * NBH;
+    hipError_t e;
+    for (int k = 0; k < m - 2; k += NBH) {
+        const int nb = std::min(NBH, m - 2 - k);
+        int nchunk = 1;
+        for (int j = 0; j < nb; ++j) {
+            const int c = k + j;
+            hipLaunchKernelGGL(k_hh_col, dim3(1), dim3(HT), 0, s, A, lda, m, k, j, 1, V, Y, Tm, W, tau, part,
+                               nchunk);
+            const int ncol = m - (c + 1);
+            nchunk = std::max(1, std::min(nchunk_max, std::min(ncol / 16, (1024 + rblk - 1) / rblk)));
+            hipLaunchKernelGGL(k_hh_gemv, dim3(rblk, nchunk), dim3(256), 0, s, A, lda, m, c, V + (size_t)j * mm,
+                               part, nchunk);
+        }
+        // complete Y(:, nb-1)
+        hipLaunchKernelGGL(k_hh_col, dim3(1), dim3(HT), 0, s, A, lda, m, k, nb, 0, V, Y, Tm, W, tau, part, nchunk);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int c1 = k + nb; // first column right of the panel
+        const int r0 = k + 1;  // first row the reflectors touch
+        // right: A(0:m, c1:m) -= Y V(c1:m, :)^T
+        if ((e = hh_gemm(m, m - c1, nb, -1.0, Y, m, 0, V + c1, m, 1, 1.0, A + (int64_t)c1 * lda, lda, s)) !=
+            hipSuccess)
+            return e;
+        // left: M = A(r0:m, c1:m+nr);  WL = V(r0:m, :)^T M;  M -= (V T^T)(r0:m, :) WL
+        const int ncl = m + nr - c1;
+        if ((e = hh_gemm(nb, ncl, m - r0, 1.0, V + r0, m, 1, A + r0 + (int64_t)c1 * lda, lda, 0, 0.0, WL, NBH,
+                         s)) != hipSuccess)
+            return e;
+        if ((e = hh_gemm(m - r0, nb, nb, 1.0, V + r0, m, 0, Tm, NBH, 1, 0.0, VT + r0, m, s)) != hipSuccess)
+            return e;
+        if ((e = hh_gemm(m - r0, ncl, nb, -1.0, VT + r0, m, 0, WL, NBH, 0, 1.0, A + r0 + (int64_t)c1 * lda, lda,
+                         s)) != hipSuccess)
+            return e;
+        // Z(0:nz, r0:m) <- Z (I - V T V^T):  ZW = Z V;  ZT = ZW T;  Z -= ZT V^T
+        if (Z && nz > 0) {
+            if ((e = hh_gemm(nz, nb, m - r0, 1.0, Z + (int64_t)r0 * ldz, ldz, 0, V + r0, m, 0, 0.0, ZW, nz, s)) !=
+                hipSuccess)
+                return e;
+            if ((e = hh_gemm(nz, nb, nb, 1.0, ZW, nz, 0, Tm, NBH, 0, 0.0, ZT, nz, s)) != hipSuccess) return e;
+            if ((e = hh_gemm(nz, m - r0, nb, -1.0, ZT, nz, 0, V + r0, m, 1, 1.0, Z + (int64_t)r0 * ldz, ldz, s)) !=
+                hipSuccess)
+                return e;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t restore_blocked(double *T, int64_t ldt, int nw, int ns, double *Vw, int64_t ldv, int nv, double s,
+                           double *ws, double *beta_dev, hipStream_t st)
+{
+    // the spike reflector on rows/columns 0..ns-1: T rows (all nw columns),
+    // T columns (rows 0..ns-1; the rows below are zero there), V columns
+    const size_t need = hess_ws_doubles(ns, nw - ns, nv);
+    double *hv = ws + need - (ns + 2);
+    hipLaunchKernelGGL(k_hh_spike, dim3(1), dim3(HT), 0, st, Vw, ldv, ns, s, hv);
+    hipLaunchKernelGGL(k_hh_refl_left, dim3((nw + 255) / 256), dim3(256), 0, st, T, ldt, ns, nw, hv);
+    hipLaunchKernelGGL(k_hh_refl_right, dim3((ns + 255) / 256), dim3(256), 0, st, T, ldt, ns, ns, hv);
+    hipLaunchKernelGGL(k_hh_refl_right, dim3((nv + 255) / 256), dim3(256), 0, st, Vw, ldv, ns, nv, hv);
+    hipError_t e = hipMemcpyAsync(beta_dev, hv + ns + 1, sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    return hess_reduce(T, ldt, ns, nw - ns, Vw, ldv, nv, ws, st);
+}
+
+} // namespace hqr

@@ -287,6 +287,7 @@ __device__ inline void refl3(int m, double tau, double v1, double v2, double &y0
 // single bulge every thread computes the reflector itself (no barrier before
 // the products) and the bulge column is written one step later, when no
 // thread reads it any more.
+template <int NTH = NT>
 __device__ __forceinline__ void chain_chase(SmemCore &S, double *A, int lda, int off, int ktop, int kbot, int p0, int nsteps,
                             int kend, int nb, int colhi, double *Z, int ldz, int nz)
 {
@@ -362,7 +363,7 @@ __device__ __forceinline__ void chain_chase(SmemCore &S, double *A, int lda, int
         const int nL = nact * ncL, nR = nact * perR;
         const int total = nL + nR + nact + npairs;
         if (tid == 0) fl += 4.0 * 3.0 * (double)(nL + nR) + 40.0 * (nact + npairs);
-        for (int it = tid; it < total; it += NT) {
+        for (int it = tid; it < total; it += NTH) {
             if (it < nL) {
                 const int b = blo + it / ncL, c = c0L + it % ncL;
                 const int m = M(b), r = KL(b) + 1;
@@ -1833,18 +1834,20 @@ __device__ __forceinline__ double restore_lds(Smem &S, double *T, int ldt, int n
 }
 
 // Store Z^T (order m) zero padded to order K16 into Ut (column major, ld K16).
+template <int NTH = NT>
 __device__ __forceinline__ void store_factor_t(const double *Z, int ldz, int m, double *Ut)
 {
     int K16 = (m + 15) & ~15;
-    for (int it = threadIdx.x; it < K16 * K16; it += NT) {
+    for (int it = threadIdx.x; it < K16 * K16; it += NTH) {
         int j = it % K16, k = it / K16; // Ut[j + k*K16] = Z[k][j]
         Ut[it] = (j < m && k < m) ? Z[k + j * ldz] : 0.0;
     }
 }
 
+template <int NTH = NT>
 __device__ __forceinline__ void identity_lds(double *Z, int ldz, int m, int rows)
 {
-    for (int it = threadIdx.x; it < rows * m; it += NT) {
+    for (int it = threadIdx.x; it < rows * m; it += NTH) {
         int r = it % rows, c = it / rows;
         Z[r + c * ldz] = (r == c) ? 1.0 : 0.0;
     }
@@ -1983,29 +1986,36 @@ __global__ void __launch_bounds__(NT) k_iter(double *H, int64_t ld, int n, int i
     }
 }
 
-// One workgroup per window of a chase round.
-__global__ void __launch_bounds__(NT) k_chase(double *H, int64_t ld, ChaseRound R, const double *sr,
-                                              const double *si, Defl dfl, double *Ubuf, int64_t ustride)
+// One workgroup per window of a chase round.  The window owns all of the
+// CU's LDS, so the workgroup takes 16 waves: each chase step is a few
+// thousand independent LDS-latency-bound reflector applications.
+constexpr int CHASE_NT = 1024;
+__global__ void __launch_bounds__(CHASE_NT) k_chase(double *H, int64_t ld, ChaseRound R, const double *sr,
+                                                    const double *si, Defl dfl, double *Ubuf, int64_t ustride)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem &S = *reinterpret_cast<Smem *>(smem_raw);
     const ChaseWin W = R.w[blockIdx.x];
     const int tid = threadIdx.x;
     const int a = W.a, wa = W.wa;
-    for (int it = tid; it < wa * wa; it += NT) {
+    for (int it = tid; it < wa * wa; it += CHASE_NT) {
         int r = it % wa, c = it / wa;
         S.A[r + c * LDM] = H[(a + r) + (int64_t)(a + c) * ld];
     }
-    identity_lds(S.Z, LDM, wa, wa);
+    identity_lds<CHASE_NT>(S.Z, LDM, wa, wa);
     if (tid < 2 * W.nb) {
         S.sr[tid] = sr[W.shift_off + tid];
         S.si[tid] = si[W.shift_off + tid];
     }
+    if (tid == 0) {
+        S.flops = 0.0;
+        S.nphase = S.nbstep = 0;
+    }
     __syncthreads();
-    chain_chase(S, S.A, LDM, a, R.ktop, R.kbot, W.p0, W.nsteps, W.kend, W.nb, wa - 1, S.Z, LDM, wa);
+    chain_chase<CHASE_NT>(S, S.A, LDM, a, R.ktop, R.kbot, W.p0, W.nsteps, W.kend, W.nb, wa - 1, S.Z, LDM, wa);
     // vigilant deflation behind the top bulge (entries final for this sweep)
     int nv = W.vig_hi - W.vig_lo + 1;
-    for (int i = tid; i < nv; i += NT) {
+    for (int i = tid; i < nv; i += CHASE_NT) {
         int k = W.vig_lo + i; // test subdiagonal (k+1, k)
         int kl = k - a;
         bool z = false;
@@ -2014,17 +2024,17 @@ __global__ void __launch_bounds__(NT) k_chase(double *H, int64_t ld, ChaseRound 
         S.vflag[i] = z ? 1 : 0;
     }
     __syncthreads();
-    for (int i = tid; i < nv; i += NT)
+    for (int i = tid; i < nv; i += CHASE_NT)
         if (S.vflag[i]) {
             int kl = W.vig_lo + i - a;
             S.A[(kl + 1) + kl * LDM] = 0.0;
         }
     __syncthreads();
-    for (int it = tid; it < wa * wa; it += NT) {
+    for (int it = tid; it < wa * wa; it += CHASE_NT) {
         int r = it % wa, c = it / wa;
         H[(a + r) + (int64_t)(a + c) * ld] = S.A[r + c * LDM];
     }
-    store_factor_t(S.Z, LDM, wa, Ubuf + (int64_t)W.slot * ustride);
+    store_factor_t<CHASE_NT>(S.Z, LDM, wa, Ubuf + (int64_t)W.slot * ustride);
 }
 
 // Corner deflation of a large AED window held in global memory.
@@ -2290,6 +2300,14 @@ __global__ void k_zero_lower(double *H, int64_t ld, int n)
     for (int r = c + 2 + threadIdx.x; r < n; r += blockDim.x) H[r + (int64_t)c * ld] = 0.0;
 }
 
+// non-finite entries anywhere in the n x n matrix (column per workgroup)
+__global__ void k_check_finite_full(const double *A, int64_t ld, int n, int *flag)
+{
+    const int c = blockIdx.x;
+    for (int r = threadIdx.x; r < n; r += blockDim.x)
+        if (!isfinite(A[r + (int64_t)c * ld])) atomicOr(flag, 1);
+}
+
 __global__ void k_check_finite(const double *H, int64_t ld, int n, int *flag)
 {
     int c = blockIdx.x;
@@ -2417,7 +2435,7 @@ hipError_t launch_chase(double *H, int64_t ld, const ChaseRound &r, const double
 {
     hipError_t e = prep((const void *)k_chase);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_chase, dim3(r.nwin), dim3(NT), smem_bytes(), s, H, ld, r, sr, si, dfl, Ubuf,
+    hipLaunchKernelGGL(k_chase, dim3(r.nwin), dim3(CHASE_NT), smem_bytes(), s, H, ld, r, sr, si, dfl, Ubuf,
                        ustride);
     return hipGetLastError();
 }
@@ -2454,6 +2472,12 @@ hipError_t launch_block_eigs(const double *T, int64_t ldt, int m, double *wr, do
 {
     if (m <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_block_eigs, dim3((m + 255) / 256), dim3(256), 0, s, T, ldt, m, wr, wi);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite_full(const double *A, int64_t ld, int n, int *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_finite_full, dim3(n), dim3(256), 0, s, A, ld, n, flag);
     return hipGetLastError();
 }
 

@@ -31,11 +31,11 @@ def _say(m):
     sys.stdout.flush()
 
 
-def hess_lu_residual(H, lam, iters=1, seed=0):
-    """Residual ||(H - lam I) x|| / ||x|| after one step of inverse iteration from a
-    random start (an upper bound on sigma_min(H - lam I)) with the
-    partially pivoted LU of the Hessenberg matrix H - lam I (row operations
-    vectorized over columns)."""
+def hess_inverse_vector(H, lam, iters=1, seed=0):
+    """Approximate eigenvector for lam by inverse iteration from a random start
+    with the partially pivoted LU of the Hessenberg matrix H - lam I (row
+    operations vectorized over columns).  Returns (x, ||(H - lam I) x||) with
+    ||x|| = 1; the residual bounds sigma_min(H - lam I) from above."""
     n = H.shape[0]
     A = np.array(H, dtype=complex)
     A[np.arange(n), np.arange(n)] -= lam
@@ -57,22 +57,41 @@ def hess_lu_residual(H, lam, iters=1, seed=0):
     U_ = np.triu(LU)
     rng = np.random.default_rng(seed)
     x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x /= np.linalg.norm(x)
     import scipy.linalg as sla
     for _ in range(iters):
-        b = x / np.linalg.norm(x) * 1e-200  # scaled so that huge solutions stay finite
+        b = x * 1e-200  # scaled so that huge solutions stay finite
         for k in range(n - 1):  # apply the row operations to b
             if piv[k]:
                 b[k], b[k + 1] = b[k + 1], b[k]
             b[k + 1] -= mult[k] * b[k]
         with np.errstate(over="ignore", invalid="ignore"):
-            x = sla.solve_triangular(U_, b, check_finite=False)
-        nx = np.linalg.norm(x)
-        if not np.isfinite(nx):
-            # ||x|| > 1e108 for ||b|| = 1e-200: sigma_min(H - lam I) < 1e-308
-            return 0.0
-        x /= nx
-    r = A @ x
-    return np.linalg.norm(r)
+            y = sla.solve_triangular(U_, b, check_finite=False)
+        my = np.abs(y).max()
+        if not np.isfinite(my):
+            # ||y|| > 1e108 for ||b|| = 1e-200: sigma_min(H - lam I) < 1e-308
+            return x, 0.0
+        y = y / my  # scaled first: the squares of entries near 1e-200 underflow
+        x = y / np.linalg.norm(y)
+    return x, np.linalg.norm(A @ x)
+
+
+def hess_lu_residual(H, lam, iters=1, seed=0):
+    """Residual ||(H - lam I) x|| / ||x|| after inverse iteration (an upper
+    bound on sigma_min(H - lam I))."""
+    return hess_inverse_vector(H, lam, iters, seed)[1]
+
+
+def eig_condition_at(H, lam):
+    """kappa = ||x|| ||y|| / |y^H x| for the eigenvalue lam of the Hessenberg
+    H: right vector x by inverse iteration on H - lam I, left vector y by
+    inverse iteration on the upper Hessenberg J (H - lam I)^H J (J the
+    reversal), y = J z."""
+    x, _ = hess_inverse_vector(H, lam, iters=2, seed=1)
+    B = np.conj(H.T)[::-1, ::-1].copy()
+    z, _ = hess_inverse_vector(B, np.conj(lam), iters=2, seed=2)
+    y = z[::-1]
+    return 1.0 / max(abs(np.vdot(y, x)), 1e-300)
 
 
 def solve_gpu_colmajor(Hd, params):
@@ -114,22 +133,23 @@ def test_config1_gaussian_n4096(gpu):
         res = hess_lu_residual(H, w[idx])
         assert res <= 100 * n * U * hn, (idx, w[idx], res)
     # every eigenvalue against the oracle's on the same input (same ns, nw),
-    # matched one to one, within 1e-10 kappa_i ||H||_F
+    # matched one to one, within 1e-10 kappa_i ||H||_F; kappa_i (from inverse
+    # iteration, O(n^2) each) only where the pair differs by more than
+    # 1e-10 ||H||_F
     import time
     t0 = time.perf_counter()
     _, _, wo, oinfo, _ = oracle.schur(H, want_q=False, ns=64, nw=256)
     _say(f"oracle n={n}: {time.perf_counter() - t0:.1f} s")
     assert oinfo == 0
-    t0 = time.perf_counter()
-    lam, kap = checks.eig_condition(H)
-    _say(f"condition numbers: {time.perf_counter() - t0:.1f} s, max kappa {kap.max():.3e}")
     r, c, d = checks.match(w, wo)
-    r2, c2, _ = checks.match(wo, lam)
-    kap_o = np.empty(n)
-    kap_o[r2] = kap[c2]
-    tol = 1e-10 * np.maximum(kap_o[c], 1.0) * hn
-    _say(f"matched {len(d)} eigenvalues: worst |dl|/tol {np.max(d / tol):.3e}")
-    assert len(d) == n and np.all(d <= tol)
+    assert len(d) == n
+    base = 1e-10 * hn
+    far = np.nonzero(d > base)[0]
+    _say(f"matched {n} eigenvalues: worst |dl| {d.max():.3e}, {len(far)} beyond 1e-10 ||H||_F")
+    for i in far:
+        kap = eig_condition_at(H, wo[c[i]])
+        _say(f"  pair {i}: |dl| {d[i]:.3e} kappa {kap:.3e}")
+        assert d[i] <= base * max(kap, 1.0)
 
 
 def nearest_both_ways(w, ref):
@@ -144,8 +164,6 @@ def nearest_both_ways(w, ref):
     return max(d1.max(), d2.max())
 
 
-@pytest.mark.skipif(os.environ.get("HQR_FULLSIZE_16K", "0") != "1",
-                    reason="n=16384 takes minutes; set HQR_FULLSIZE_16K=1")
 def test_config2_prescribed_n16384(gpu):
     import torch
     n = 16384
