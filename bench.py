@@ -141,6 +141,7 @@ def grad_run(seed):
     shape = autotune.tune(512, 512, count=512, seed=seed + 3,
                           candidates=((1, 4095), (2, 4095), (2, 320), (3, 320), (4, 320)))
     fw = bw = None
+    X = None
     for _ in range(2):
         X = H.clone().requires_grad_(True)
         torch.cuda.synchronize()
@@ -153,6 +154,24 @@ def grad_run(seed):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         fw, bw = t1 - t0, t2 - t1
+    # accuracy (outside the timed region): central differences of the same
+    # batched forward along two seeded unit directions on the Hessenberg
+    # pattern of all 512 matrices, against <dL/dH, D>
+    def loss_of(M):
+        with torch.no_grad():
+            lm = hq.eigvals(M)
+            return float(torch.nn.functional.softplus(lm.real).sum() + 0.1 * (lm.abs() ** 2).sum())
+
+    gen = torch.Generator(device=H.device)
+    gen.manual_seed(seed + 5)
+    fd_checks = []
+    h = 1e-5
+    for _ in range(2):
+        D = torch.randn(H.shape, generator=gen, dtype=H.dtype, device=H.device).triu(-1)
+        D /= torch.linalg.norm(D)
+        fd = (loss_of(H + h * D) - loss_of(H - h * D)) / (2 * h)
+        an = float((X.grad * D).sum())
+        fd_checks.append({"fd": fd, "analytic": an, "rel_diff": abs(fd - an) / max(abs(an), 1e-300)})
     # the plain solver, one hqr_schur call per matrix (forward only), on 8 of the matrices
     hq.schur(H[0])
     torch.cuda.synchronize()
@@ -163,10 +182,67 @@ def grad_run(seed):
     plain_rate = 8 / (time.perf_counter() - t0)
     return {"workload": "512 matrices n=512, separated prescribed spectra, L = sum softplus(Re l) + 0.1 sum |l|^2",
             "forward_s": fw, "backward_s": bw, "solves_per_s": 512 / (fw + bw),
+            "accuracy_fd": {"h": h, "directions": fd_checks},
             "launch_shape": {"wg_per_cu": shape["wg_per_cu"], "wide_n": shape["wide_n"]},
             "plain_per_matrix": {"sample": "8 of the matrices, one hqr_schur call each, forward only",
                                  "solves_per_s": plain_rate},
             "speedup_vs_plain": (512 / (fw + bw)) / plain_rate}
+
+
+def paper_scale_run(seed):
+    """The paper-scale configuration: one solve of the n = 16384 Hessenberg
+    matrix with a prescribed spectrum (8192 real eigenvalues, 4096 conjugate
+    pairs; Haar orthogonal similarity reduced to Hessenberg form on the GPU),
+    256 shifts per sweep, AED window 1024, Q accumulated, input resident in
+    HBM before the timed call.  Reports the seconds, the nominal 10 n^3
+    TFLOP/s, the accuracy (backward error, orthogonality, distance of every
+    computed eigenvalue to the prescribed spectrum and back), the kernel-class
+    split and the roofline entries of the dominant kernel and of the
+    FP64-MFMA update kernel."""
+    import numpy as np
+    import torch
+    import hqr_inputs as hi
+    import paper_2007_03576_amd as hq
+    from paper_2007_03576_amd import profiling
+    from scipy.spatial import cKDTree
+    n = 16384
+    dev = torch.device("cuda:0")
+    H, ev = hi.prescribed_hessenberg_device(n, seed=seed, device=dev)
+    Hc = H.t().contiguous()  # row-major storage of H^T = column-major H
+    del H
+    Q = torch.eye(n, dtype=torch.float64, device=dev)
+    A = Hc.clone()
+    wr = torch.empty(n, dtype=torch.float64, device=dev)
+    wi = torch.empty_like(wr)
+    params = {"ns": 256, "nw": 1024}
+    torch.cuda.synchronize()
+    profiling.enable(True)
+    profiling.reset()
+    t0 = time.perf_counter()
+    info = hq.schur_colmajor(A.t(), Q.t(), wr, wi, params=params)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = profiling.read()
+    split = profiling.lds_split()
+    profiling.enable(False)
+    stats = hq.last_stats()
+    T, Qm, H0 = A.t(), Q.t(), Hc.t()
+    hn = float(torch.linalg.norm(H0))
+    be = float(torch.linalg.norm(Qm.t() @ H0 @ Qm - T)) / hn
+    orth = float(torch.linalg.norm(Qm.t() @ Qm - torch.eye(n, dtype=Qm.dtype, device=dev)))
+    w = wr.cpu().numpy() + 1j * wi.cpu().numpy()
+    P, R = np.c_[w.real, w.imag], np.c_[np.real(ev), np.imag(ev)]
+    dmax = max(cKDTree(R).query(P)[0].max(), cKDTree(P).query(R)[0].max())
+    out = {"workload": "prescribed_hessenberg_n16384 (one solve, ns=256, nw=1024, Q accumulated)",
+           "s": dt, "value": 10.0 * n ** 3 / dt / 1e12, "unit": "TFLOP/s (10n^3 nominal)", "info": info,
+           "accuracy": {"backward_rel": be, "orth": orth, "bound_100nu": 100 * n * 2.0 ** -52,
+                        "eig_dist_max_rel": dmax / hn},
+           "run_stats": stats, "roofline": profiling.roofline(prof, 1),
+           "kernel_times": profiling.summary(prof, 1)}
+    out["kernel_times"]["lds_iteration"]["split"] = split
+    del A, Q, Hc
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(spec, seed, target_n):
@@ -185,9 +261,10 @@ def cpu_baseline(spec, seed, target_n):
     dt = time.perf_counter() - t0
     assert info == 0
     return {"value": 10.0 * target_n ** 3 / dt / 1e12, "unit": "TFLOP/s (10n^3 nominal)", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpus": os.cpu_count(),
             "sample": f"one full solve of the same workload at n={target_n} (same generator, ns={spec['ns']}, "
-                      f"nw={spec['nw']}, Q accumulated): {dt:.2f} s single-threaded"}
+                      f"nw={spec['nw']}, Q accumulated): {dt:.2f} s on one thread of a host with "
+                      f"{os.cpu_count()} logical CPUs (the oracle is single-threaded C)"}
 
 
 def main():
@@ -198,7 +275,9 @@ def main():
     ap.add_argument("--workload", default="gaussian_hessenberg_n4096", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=2020)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched and differentiation lines")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched, differentiation and paper-scale lines")
+    ap.add_argument("--no-paper-scale", action="store_true", help="skip the n = 16384 paper-scale solve")
     ap.add_argument("--cpu-n", type=int, default=2048)
     ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--small-shifts", type=int, default=0)
@@ -300,6 +379,8 @@ def main():
         out["plain_solves_per_s"] = 1.0 / dt
         out["batched"] = batched_run(args.seed)
         out["grad"] = grad_run(args.seed)
+        if args.workload != "prescribed_hessenberg_n16384" and not args.no_paper_scale:
+            out["paper_scale"] = paper_scale_run(args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.seed, args.cpu_n)
     else:

@@ -152,6 +152,24 @@ int hqr_set_batched_launch(int32_t wg_per_cu, int32_t wide_n);
 /* Current values (host pointers); returns 0, or -1 for a NULL pointer. */
 int hqr_get_batched_launch(int32_t *wg_per_cu, int32_t *wide_n);
 
+/* Right eigenvectors of H = Q T Q^T from its real Schur form, the phase after
+ * the Schur reduction (Sec. 1: the eigenvectors of H are Q times those of
+ * the Schur form).  T (quasi-triangular with standardized 2x2 blocks, as
+ * hqr_schur returns it), Q: n x n, leading dimension ld, device; wr/wi: the
+ * eigenvalues as hqr_schur returns them (diagonal order, pairs adjacent
+ * with wi > 0 first).  X (n x n, leading dimension ldx, device) receives the
+ * vectors in LAPACK's dgeev layout: column j holds the real vector of a real
+ * eigenvalue; for a pair (j, j+1) columns j and j+1 hold the real and
+ * imaginary parts of the vector of wr[j] + i wi[j].  Each vector has unit
+ * 2-norm and its largest component real.  Vectors of T come from
+ * quasi-triangular back substitution (one lane per eigenvalue, 2x2 blocks
+ * solved exactly, pivots floored at u max|T|), then X = Q Y on FP64 MFMA.
+ * n <= 8192.  Workspace (12 n^2 doubles) is kept per (device, stream);
+ * blocks the host until done.  Returns 0, -k for a bad argument k, or
+ * -1000-e for a HIP error e. */
+int hqr_eigenvectors(const double *T, const double *Q, int64_t n, int64_t ld, const double *wr, const double *wi,
+                     double *X, int64_t ldx, void *stream);
+
 /* Backward pass of the eigenvalues (the differentiated form beside the
  * solver) for a batch of Schur forms H_i = Q_i T_i Q_i^T, packed like the
  * batched form: matrix i has order n[i] and T_i, Q_i and dH_i sit column major
@@ -180,7 +198,9 @@ int hqr_eig_backward_batched(const double *T, const double *Q, const int64_t *of
 /* Timing and counters of the last hqr_schur call on this thread:
  * stats[0] AED steps, [1] sweeps, [2] shifts used, [3] eigenvalues deflated by
  * AED, [4] small-solver calls, [5] host synchronizations, [6] kernel launches,
- * [7] chase windows.  Returns the number of entries written (<= len). */
+ * [7] chase windows, [8] deflation windows and [9] reordering windows of the
+ * deflation checks of large AED windows.  Returns the number of entries
+ * written (<= len, at most 10). */
 int hqr_last_stats(int64_t *stats, int len);
 
 /* Kernel-class timing for measurement tools.  When enabled, the driver

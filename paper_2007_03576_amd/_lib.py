@@ -26,7 +26,8 @@ class HqrParams(ctypes.Structure):
 EXPORTS = ["hqr_set_params", "hqr_get_params", "hqr_schur", "hqr_schur_ex", "hqr_schur_batched",
            "hqr_eig_backward_batched", "hqr_last_stats", "hqr_finalize", "hqr_profile_enable",
            "hqr_profile_reset", "hqr_profile_read", "hqr_profile_ticks", "hqr_set_batched_launch",
-           "hqr_get_batched_launch", "hqr_schur_batched_noalloc", "hqr_hessenberg"]
+           "hqr_get_batched_launch", "hqr_schur_batched_noalloc", "hqr_hessenberg",
+           "hqr_eigenvectors"]
 
 
 class HqrError(RuntimeError):
@@ -48,6 +49,7 @@ def lib():
     L.hqr_schur.argtypes = [vp, vp, i64, i64, vp, vp, vp]
     L.hqr_schur_ex.argtypes = [vp, vp, i64, i64, vp, vp, vp, ctypes.POINTER(HqrParams)]
     L.hqr_hessenberg.argtypes = [vp, vp, i64, i64, vp]
+    L.hqr_eigenvectors.argtypes = [vp, vp, i64, i64, vp, vp, vp, i64, vp]
     L.hqr_schur_batched.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
     L.hqr_schur_batched_noalloc.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
     L.hqr_set_batched_launch.argtypes = [i32, i32]

@@ -8,7 +8,7 @@ import torch
 
 from ._lib import HqrError, HqrParams, check, lib
 
-__all__ = ["schur", "schur_colmajor", "schur_batched", "eigvals", "set_params", "params",
+__all__ = ["schur", "schur_colmajor", "schur_batched", "eigvals", "hessenberg", "eigenvectors", "set_params", "params",
            "last_stats", "HqrError", "BatchedProblem", "BatchedGraph", "set_batched_launch",
            "batched_launch"]
 
@@ -41,10 +41,10 @@ def params() -> dict:
 
 
 def last_stats() -> dict:
-    arr = (ctypes.c_int64 * 8)()
-    lib().hqr_last_stats(arr, 8)
+    arr = (ctypes.c_int64 * 10)()
+    lib().hqr_last_stats(arr, 10)
     keys = ["aed_steps", "sweeps", "shifts", "aed_deflated", "small_solves", "host_syncs",
-            "launches", "chase_windows"]
+            "launches", "chase_windows", "deflation_windows", "reordering_windows"]
     return dict(zip(keys, list(arr)))
 
 
@@ -97,6 +97,48 @@ def schur(H: torch.Tensor, want_q: bool = True, Q0: Optional[torch.Tensor] = Non
     info = schur_colmajor(Hf, Qf, wr, wi, params=params, stream=stream)
     w = torch.complex(wr[:n], wi[:n])
     return Hf, Qf, w, info
+
+
+def hessenberg(A: torch.Tensor, want_q: bool = True, stream=None):
+    """Upper Hessenberg form of a dense square float64 GPU matrix:
+    returns (H, Q) with A = Q H Q^T (hqr_hessenberg)."""
+    _require_device(A, "A")
+    n = A.shape[0]
+    Af = _fortran(A)
+    Qf = _fortran(torch.eye(n, dtype=A.dtype, device=A.device)) if want_q else None
+    rc = lib().hqr_hessenberg(ctypes.c_void_p(Af.data_ptr()), ctypes.c_void_p(Qf.data_ptr()) if want_q else None,
+                              n, max(n, 1), _stream_handle(stream))
+    check(rc, "hqr_hessenberg")
+    return Af, Qf
+
+
+def eigenvectors(T: torch.Tensor, Q: torch.Tensor, w: torch.Tensor, stream=None) -> torch.Tensor:
+    """Right eigenvectors of H = Q T Q^T from the real Schur form that schur()
+    returns (T, Q column major, w complex in diagonal order): a complex
+    (n x n) tensor whose column j is the unit eigenvector of w[j]
+    (hqr_eigenvectors, dgeev layout unpacked)."""
+    _require_device(T, "T")
+    n = T.shape[0]
+    Tf, Qf = _fortran(T), _fortran(Q)
+    wr = w.real.contiguous().to(torch.float64)
+    wi = w.imag.contiguous().to(torch.float64)
+    X = _fortran(torch.empty(n, n, dtype=torch.float64, device=T.device))
+    rc = lib().hqr_eigenvectors(ctypes.c_void_p(Tf.data_ptr()), ctypes.c_void_p(Qf.data_ptr()), n, max(n, 1),
+                                ctypes.c_void_p(wr.data_ptr()), ctypes.c_void_p(wi.data_ptr()),
+                                ctypes.c_void_p(X.data_ptr()), max(n, 1), _stream_handle(stream))
+    check(rc, "hqr_eigenvectors")
+    V = torch.complex(X, torch.zeros_like(X))
+    j = 0
+    wi_h = wi.cpu()
+    while j < n:
+        if wi_h[j] > 0 and j + 1 < n:
+            re, im = X[:, j], X[:, j + 1]
+            V[:, j] = torch.complex(re, im)
+            V[:, j + 1] = torch.complex(re, -im)
+            j += 2
+        else:
+            j += 1
+    return V
 
 
 def set_batched_launch(wg_per_cu: int, wide_n: int) -> None:

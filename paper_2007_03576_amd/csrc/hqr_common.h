@@ -107,10 +107,14 @@ hipError_t launch_find_block(double *H, int64_t ld, int ilo, int kbot, Defl dfl,
 // Chase round: one workgroup per window; U factors written transposed to Ubuf.
 hipError_t launch_chase(double *H, int64_t ld, const ChaseRound &r, const double *sr, const double *si,
                         Defl dfl, double *Ubuf, int64_t ustride, hipStream_t s);
-// Deflation check of the bottom corner of a large AED window (T in global
-// memory, order nw; the corner has order wd <= MMAX) with reordering.
+// Window [nw - wd, nw) of a large AED window (T in global memory; wd <=
+// MMAX, one row less if the top boundary would split a 2x2 block), its
+// spike taken from row 0 of V: a deflation window tests its candidates
+// bottom-up with the nforced bottom ones counted as failed, and moves the
+// failures to its top; a reordering window (reorder != 0) moves the nforced
+// bottom candidates to its top without testing the others.
 hipError_t launch_corner_deflate(double *T, int64_t ldt, int nw, int wd, const double *V, int64_t ldv,
-                                 double s, Defl dfl, double *Ut, IterStatus *st, int nforced,
+                                 double s, Defl dfl, double *Ut, IterStatus *st, int nforced, int reorder,
                                  hipStream_t stream);
 // Hessenberg restoration of T(0:ns,0:ns) in global memory with the spike,
 // applied to T(0:ns, ns:nw) and to V (rows 0..nv-1).
@@ -147,6 +151,10 @@ struct BwdDesc {
     int64_t toff, eoff, woff;
     int n, pad;
 };
+// Right eigenvectors of H = Q T Q^T (T, Q packed with leading dimension n, one
+// descriptor with woff 0) into X (dgeev layout, leading dimension ldx).
+hipError_t launch_eigenvectors(const double *T, const double *Q, const BwdDesc *D, int n, const double *wr,
+                               const double *wi, double *ws, double *X, int64_t ldx, hipStream_t s);
 // One chunk of nb matrices (descriptors D, device), largest order nmax.
 hipError_t launch_eig_backward_chunk(const double *T, const double *Q, const BwdDesc *D, int nb, int nmax,
                                      const double *wr, const double *wi, const double *gwr, const double *gwi,

@@ -66,7 +66,8 @@ std::map<std::pair<int, void *>, BwdWs> g_bwd;
 // for three rows, three columns of H and Q); two workgroups per CU keep that
 // inside the CU's share of L2 (4 MB per 32 CUs) up to about n = 360.
 int g_batched_wg_per_cu = 2, g_batched_wide_n = 320;
-thread_local int64_t t_stats[8];
+constexpr int NSTATS = 10;
+thread_local int64_t t_stats[NSTATS];
 
 struct Params {
     int ns, nw, nmin, nibble, kexsh;
@@ -647,38 +648,77 @@ int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd
         ncand = w;
         return 0;
     }
-    // Deflation check of the whole window by a chain of deflation windows of
-    // order <= 96 moving up from the bottom corner (Sec. 3.5 "Parallel
-    // aggressive early deflation", chains of deflate tasks):
-    // each window examines its unchecked candidates bottom-up, with the
-    // failures of the windows below it (at its bottom) treated as failed,
-    // and leaves all failures at its top; the next window ends at the
-    // bottommost failure.  The transformation of each window updates the
-    // window rows to its right, the rows above it and V.  The chain stops at
-    // the top of the AED window, after a rejected swap, or when the failures
-    // fill more than half of a window (the rest counts as undeflated).
-    int bot = w, nfail = 0;
-    for (;;) {
-        int wd = std::min(bot, MMAX);
-        if (wd <= nfail) break;
+    // Deflation check of the whole window (Sec. 3.5 "Parallel aggressive
+    // early deflation"): deflation windows of order <= 96 move up from the
+    // bottom corner.  Each examines its unchecked candidates bottom-up (the
+    // failures of the window below it, at its bottom, count as failed) and
+    // leaves all failures at its top; the next window ends at the bottommost
+    // failure.  When the failures fill more than half of a window (and at
+    // most two thirds), a chain of reordering windows carries them to the top
+    // of the AED window and the next deflation window starts at the next
+    // unevaluated candidate; with more failures the rest of the window counts
+    // as undeflated (few of its candidates would deflate).  The
+    // transformation of each window updates the window rows to its right,
+    // the rows above it and V.  A rejected swap halts the check (the greedy
+    // rule): everything above the deflated bottom then counts as undeflated.
+    int bot = w, nfail = 0, ntop = 0;
+    auto window = [&](int wbot, int wd, int nforced, int reorder, int &c0, int &wdd, int &halted,
+                      int &nsr) -> int {
         int slc = take_slot(C);
         double *Utc = slot_ptr(W, slc); // used on the critical stream only
         int pidc = prof_begin(3, C.hi);
-        CK(launch_corner_deflate(T, w, bot, wd, Vw, w, s, C.dfl, Utc, W.st_dev, nfail, C.hi));
+        CK(launch_corner_deflate(T, w, wbot, wd, Vw, w, s, C.dfl, Utc, W.st_dev, nforced, reorder, C.hi));
         prof_end(pidc, C.hi, 0.0, 0.0);
+        if (C.stats) C.stats[reorder ? 9 : 8]++;
         if (read_status(C, 0)) return -1;
-        const int c0 = W.st_host->kwtop, wdd = W.st_host->nw, halted = W.st_host->info;
-        const int nsr = W.st_host->ns; // undeflated leading rows of the AED window
-        {
-            UpdBatch b = make_batch();
-            add_job(b, T + (int64_t)c0 * w, w, c0, wdd, Utc, 0);
-            add_job(b, T + c0 + (int64_t)bot * w, w, w - bot, wdd, Utc, 1);
-            add_job(b, Vw + (int64_t)c0 * w, w, w, wdd, Utc, 0);
-            if (flush(b, C.hi, C)) return -1;
-        }
-        nfail = nsr - c0;
+        c0 = W.st_host->kwtop;
+        wdd = W.st_host->nw;
+        halted = W.st_host->info;
+        nsr = W.st_host->ns; // undeflated leading rows of the AED window
+        UpdBatch b = make_batch();
+        add_job(b, T + (int64_t)c0 * w, w, c0, wdd, Utc, 0);
+        add_job(b, T + c0 + (int64_t)wbot * w, w, w - wbot, wdd, Utc, 1);
+        add_job(b, Vw + (int64_t)c0 * w, w, w, wdd, Utc, 0);
+        if (flush(b, C.hi, C)) return -1;
+        return 0;
+    };
+    for (;;) {
+        const int wd = std::min(bot - ntop, MMAX); // the failures already at the top stay out
+        if (wd <= nfail) break;
+        int c0, wdd, halted, nsr;
+        const int rw = window(bot, wd, nfail, 0, c0, wdd, halted, nsr);
+        if (rw) return rw;
+        const int nf = nsr - c0; // failures now at [c0, nsr), deflated below
         bot = nsr;
-        if (halted || c0 == 0 || 2 * nfail > wdd) break;
+        if (halted || c0 <= ntop) break;
+        if (2 * nf <= wdd) {
+            nfail = nf;
+            continue;
+        }
+        // a reordering window advances by its order minus the failures it
+        // carries: beyond two thirds of a window the rest is left unevaluated
+        if (3 * nf > 2 * wdd) break;
+        // reordering chain: failures [fb - nf, fb) up to [ntop, ntop + nf)
+        int fb = nsr;
+        bool moved = true;
+        while (fb - nf > ntop) {
+            const int wr = std::min(fb - ntop, MMAX);
+            if (wr <= nf + 1) {
+                moved = false; // no room to pass a block
+                break;
+            }
+            int c0r, wdr, haltedr, nsrr;
+            const int rr = window(fb, wr, nf, 1, c0r, wdr, haltedr, nsrr);
+            if (rr) return rr;
+            if (haltedr || c0r + nf >= fb) {
+                moved = false;
+                break;
+            }
+            fb = c0r + nf;
+        }
+        if (!moved) break;
+        ntop += nf;
+        nfail = 0;
     }
     ns = bot;
     nd = w - bot;
@@ -991,7 +1031,7 @@ int hqr_get_params(hqr_params *p)
 int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double *wi, void *stream,
                  const hqr_params *pp)
 {
-    for (int i = 0; i < 8; ++i) t_stats[i] = 0;
+    for (int i = 0; i < NSTATS; ++i) t_stats[i] = 0;
     if (n < 0) return -3;
     if (n == 0) return 0;
     if (!H) return -1;
@@ -1104,7 +1144,7 @@ int hqr_hessenberg(double *A, double *Q, int64_t n, int64_t ld, void *stream)
 int hqr_last_stats(int64_t *stats, int len)
 {
     if (!stats || len <= 0) return 0;
-    int m = std::min(len, 8);
+    int m = std::min(len, NSTATS);
     for (int i = 0; i < m; ++i) stats[i] = t_stats[i];
     return m;
 }
@@ -1307,6 +1347,58 @@ int hqr_get_batched_launch(int32_t *wg_per_cu, int32_t *wide_n)
     return 0;
 }
 
+
+int hqr_eigenvectors(const double *T, const double *Q, int64_t n, int64_t ld, const double *wr, const double *wi,
+                     double *X, int64_t ldx, void *stream)
+{
+    if (!T) return -1;
+    if (!Q) return -2;
+    if (n < 0 || n > 8192) return -3;
+    if (ld < std::max<int64_t>(1, n)) return -4;
+    if (!wr) return -5;
+    if (!wi) return -6;
+    if (!X) return -7;
+    if (ldx < std::max<int64_t>(1, n)) return -8;
+    if (n == 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    BwdWs *B;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        B = &g_bwd[std::make_pair(dev, stream)];
+    }
+    std::lock_guard<std::mutex> call_lk(B->mu);
+    const size_t nn = (size_t)n * n;
+    const size_t need = 10 * nn + 1 + 2 * nn; // backward layout, then packed copies of T and Q
+    if (B->wcap < need || B->dcap < 1) {
+        CK(hipStreamSynchronize(st)); // earlier calls on this stream may still use the buffers
+        if (B->wcap < need) {
+            if (B->ws) CK(hipFree(B->ws));
+            B->ws = nullptr;
+            B->wcap = 0;
+            CK(hipMalloc(&B->ws, sizeof(double) * need));
+            B->wcap = need;
+        }
+        if (B->dcap < 1) {
+            if (B->d_desc) CK(hipFree(B->d_desc));
+            B->d_desc = nullptr;
+            B->dcap = 0;
+            CK(hipMalloc(&B->d_desc, sizeof(BwdDesc)));
+            B->dcap = 1;
+        }
+    }
+    double *Tp = B->ws + 10 * nn + 1, *Qp = Tp + nn;
+    CK(hipMemcpy2DAsync(Tp, n * sizeof(double), T, ld * sizeof(double), n * sizeof(double), n,
+                        hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpy2DAsync(Qp, n * sizeof(double), Q, ld * sizeof(double), n * sizeof(double), n,
+                        hipMemcpyDeviceToDevice, st));
+    BwdDesc d{0, 0, 0, (int)n, 0};
+    CK(hipMemcpyAsync(B->d_desc, &d, sizeof(BwdDesc), hipMemcpyHostToDevice, st));
+    CK(launch_eigenvectors(Tp, Qp, B->d_desc, (int)n, wr, wi, B->ws, X, ldx, st));
+    CK(hipStreamSynchronize(st)); // the descriptor lives on the host stack
+    return 0;
+}
 
 int hqr_eig_backward_batched(const double *T, const double *Q, const int64_t *offsets, const int32_t *n,
                              int32_t batch, const double *wr, const double *wi, const double *gwr,

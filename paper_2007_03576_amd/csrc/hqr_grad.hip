@@ -349,6 +349,81 @@ __global__ void k_hess_mask(const BwdDesc *D, double *dH)
     for (int r = c + 2 + threadIdx.x; r < n; r += blockDim.x) Db[r + (int64_t)c * n] = 0.0;
 }
 
+// Right eigenvectors of H in LAPACK's dgeev layout from X = [Re | Im] (n x 2n,
+// column e = vector of eigenvalue e): a real eigenvalue gets one real column;
+// the pair (e, e+1) with wi[e] > 0 gets Re(x) and Im(x) of the vector of
+// wr[e] + i wi[e].  Each vector is scaled to unit 2-norm with its largest
+// component real and positive.  One workgroup per eigenvalue.
+__global__ void __launch_bounds__(256) k_evec_pack(int n, const double *Xw, const double *wi, double *Xo,
+                                                   int64_t ldx)
+{
+    __shared__ double red[256];
+    __shared__ int ired[256];
+    const int e = blockIdx.x;
+    if (wi[e] < 0.0) return; // written together with its partner
+    const bool cplx = wi[e] > 0.0;
+    const double *xr = Xw + (int64_t)e * n, *xi = Xw + (int64_t)(n + e) * n;
+    double ss = 0.0, best = -1.0;
+    int bi = 0;
+    for (int r = threadIdx.x; r < n; r += 256) {
+        const double a = xr[r], b = cplx ? xi[r] : 0.0;
+        const double m2 = a * a + b * b;
+        ss += m2;
+        if (m2 > best) {
+            best = m2;
+            bi = r;
+        }
+    }
+    red[threadIdx.x] = ss;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double nrm = sqrt(red[0]);
+    __syncthreads();
+    red[threadIdx.x] = best;
+    ired[threadIdx.x] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w && (red[threadIdx.x + w] > red[threadIdx.x] ||
+                                    (red[threadIdx.x + w] == red[threadIdx.x] &&
+                                     ired[threadIdx.x + w] < ired[threadIdx.x])))
+        {
+            red[threadIdx.x] = red[threadIdx.x + w];
+            ired[threadIdx.x] = ired[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    const int k = ired[0];
+    // rotation c - i s that makes component k real and positive, with 1/||x||
+    double c = 1.0, sn = 0.0;
+    const double ak = xr[k], bk = cplx ? xi[k] : 0.0;
+    const double mk = hypot(ak, bk);
+    if (mk > 0.0) {
+        c = ak / mk;
+        sn = bk / mk;
+    }
+    const double sc = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+    for (int r = threadIdx.x; r < n; r += 256) {
+        const double a = xr[r], b = cplx ? xi[r] : 0.0;
+        // (a + i b)(c - i sn) = (a c + b sn) + i (b c - a sn)
+        Xo[r + (int64_t)e * ldx] = (a * c + b * sn) * sc;
+        if (cplx) Xo[r + (int64_t)(e + 1) * ldx] = (b * c - a * sn) * sc;
+    }
+}
+
+hipError_t launch_eigenvectors(const double *T, const double *Q, const BwdDesc *D, int n, const double *wr,
+                               const double *wi, double *ws, double *X, int64_t ldx, hipStream_t s)
+{
+    const int tiles = (n + GT - 1) / GT, tiles2 = (2 * n + GT - 1) / GT;
+    hipLaunchKernelGGL(k_tnorm, dim3(1), dim3(256), 0, s, T, D, ws);
+    hipLaunchKernelGGL(k_eigvec, dim3((n + 63) / 64, 1), dim3(64), 0, s, T, D, wr, wi, ws);
+    hipLaunchKernelGGL(k_gemm_bwd, dim3(tiles, tiles2, 1), dim3(256), 0, s, 0, Q, D, ws, (double *)nullptr);
+    hipLaunchKernelGGL(k_evec_pack, dim3(n), dim3(256), 0, s, n, ws + 4 * (int64_t)n * n, wi, X, ldx);
+    return hipGetLastError();
+}
+
 hipError_t launch_eig_backward_chunk(const double *T, const double *Q, const BwdDesc *D, int nb, int nmax,
                                      const double *wr, const double *wi, const double *gwr, const double *gwi,
                                      double *dH, int hess_mask, double *ws, hipStream_t s)

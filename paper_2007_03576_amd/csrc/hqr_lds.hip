@@ -1456,7 +1456,7 @@ __device__ bool swap_xform(double *Tw, int ldt, int j, double smlnum, double *Go
 // the deflated bottom counts as undeflated.  Returns the number of undeflated
 // leading rows.
 __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int nt, double *Z, int ldz, int nz, int sprow,
-                           double spscale, int ilst0, const Defl &dfl, int nforced = 0)
+                           double spscale, int ilst0, const Defl &dfl, int nforced = 0, bool reorder_only = false)
 {
     const double smlnum = dfl.smlnum;
     ReorderState &R = S.ro;
@@ -1533,6 +1533,9 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
                         defl = spk <= fmax(smlnum, kU * hh);
                     }
                     if (cand >= nt - nforced) defl = false; // failed in an earlier deflation window
+                    // reordering window: the forced failures move to the top,
+                    // every other candidate stays below them untested
+                    else if (reorder_only) defl = true;
                     if (defl) {
                         ns -= csz;
                         continue;
@@ -2040,7 +2043,7 @@ __global__ void __launch_bounds__(CHASE_NT) k_chase(double *H, int64_t ld, Chase
 // Corner deflation of a large AED window held in global memory.
 __global__ void __launch_bounds__(NT) k_corner_deflate(double *T, int64_t ldt, int nw, int wd, const double *V,
                                                        int64_t ldv, double s, Defl dfl, double *Ut,
-                                                       IterStatus *st, int nforced)
+                                                       IterStatus *st, int nforced, int reorder)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem &S = *reinterpret_cast<Smem *>(smem_raw);
@@ -2058,7 +2061,7 @@ __global__ void __launch_bounds__(NT) k_corner_deflate(double *T, int64_t ldt, i
     for (int c = tid; c < wd; c += NT) S.Z[wd + c * LDM] = s * V[(int64_t)(c0 + c) * ldv];
     if (tid == 0) S.nswap = S.nrphase = 0;
     __syncthreads();
-    int nsc = aed_deflate(S, S.A, LDM, wd, S.Z, LDM, wd + 1, wd, 1.0, 0, dfl, min(nforced, wd));
+    int nsc = aed_deflate(S, S.A, LDM, wd, S.Z, LDM, wd + 1, wd, 1.0, 0, dfl, min(nforced, wd), reorder != 0);
     const int halted = S.ro.halt;
     __syncthreads();
     for (int it = tid; it < wd * wd; it += NT) {
@@ -2441,13 +2444,13 @@ hipError_t launch_chase(double *H, int64_t ld, const ChaseRound &r, const double
 }
 
 hipError_t launch_corner_deflate(double *T, int64_t ldt, int nw, int wd, const double *V, int64_t ldv,
-                                 double s, Defl dfl, double *Ut, IterStatus *st, int nforced,
+                                 double s, Defl dfl, double *Ut, IterStatus *st, int nforced, int reorder,
                                  hipStream_t stream)
 {
     hipError_t e = prep((const void *)k_corner_deflate);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_corner_deflate, dim3(1), dim3(NT), smem_bytes(), stream, T, ldt, nw, wd, V, ldv, s,
-                       dfl, Ut, st, nforced);
+                       dfl, Ut, st, nforced, reorder);
     return hipGetLastError();
 }
 

@@ -133,23 +133,30 @@ def test_config1_gaussian_n4096(gpu):
         res = hess_lu_residual(H, w[idx])
         assert res <= 100 * n * U * hn, (idx, w[idx], res)
     # every eigenvalue against the oracle's on the same input (same ns, nw),
-    # matched one to one, within 1e-10 kappa_i ||H||_F; kappa_i (from inverse
-    # iteration, O(n^2) each) only where the pair differs by more than
-    # 1e-10 ||H||_F
+    # matched one to one, within 1e-10 kappa_i ||H||_F with kappa_i from the
+    # oracle's Schur form (checks.schur_eig_condition, pinned against scipy).
+    # Most eigenvalues of this matrix are extremely ill conditioned (kappa far
+    # beyond 1e16), so two backward-stable solvers agree on them only to
+    # kappa u ||H||; the well-conditioned ones must agree tightly.
     import time
     t0 = time.perf_counter()
-    _, _, wo, oinfo, _ = oracle.schur(H, want_q=False, ns=64, nw=256)
+    To, _, wo, oinfo, _ = oracle.schur(H, want_q=False, ns=64, nw=256)
     _say(f"oracle n={n}: {time.perf_counter() - t0:.1f} s")
     assert oinfo == 0
+    t0 = time.perf_counter()
+    lam_o, kap_o = checks.schur_eig_condition(To, progress=_say)
+    _say(f"condition numbers from the oracle's Schur form: {time.perf_counter() - t0:.1f} s; "
+         f"{int(np.sum(kap_o < 1e4))} eigenvalues with kappa < 1e4")
     r, c, d = checks.match(w, wo)
     assert len(d) == n
-    base = 1e-10 * hn
-    far = np.nonzero(d > base)[0]
-    _say(f"matched {n} eigenvalues: worst |dl| {d.max():.3e}, {len(far)} beyond 1e-10 ||H||_F")
-    for i in far:
-        kap = eig_condition_at(H, wo[c[i]])
-        _say(f"  pair {i}: |dl| {d[i]:.3e} kappa {kap:.3e}")
-        assert d[i] <= base * max(kap, 1.0)
+    r2, c2, _ = checks.match(wo, lam_o)
+    kap = np.empty(n)
+    kap[r2] = kap_o[c2]
+    tol = 1e-10 * np.maximum(kap[c], 1.0) * hn
+    good = kap[c] < 1e4
+    _say(f"matched {n} eigenvalues: worst |dl|/tol {np.max(d / tol):.3e}; "
+         f"well conditioned (kappa < 1e4): {int(good.sum())}, worst |dl| {d[good].max() if good.any() else 0:.3e}")
+    assert np.all(d <= tol)
 
 
 def nearest_both_ways(w, ref):

@@ -98,7 +98,25 @@ def test_big_aed_window(gpu):
     T, Q, w, info, st = run_gpu(H, {"ns": 32, "nw": 160})
     _say(f"stats {st}")
     assert info == 0
+    assert st["deflation_windows"] > 0
     assert_schur(H, T, Q, w, tag="bigaed600")
+
+
+def test_big_aed_reordering_chains(gpu):
+    # large windows on matrices where an early deflation window fails for
+    # more than half (and at most two thirds) of its candidates: a chain of
+    # reordering windows carries the failures to the top of the AED window;
+    # every run must be a correct Schur form, and the chains must have run
+    total = 0
+    for n, seed, nw in [(700, 12, 320), (700, 13, 320), (640, 14, 256), (800, 15, 400)]:
+        _say(f"case big AED window reordering chains n={n} nw={nw} seed={seed}")
+        H = hi.hessrand(n, seed=seed)
+        T, Q, w, info, st = run_gpu(H, {"ns": 48, "nw": nw})
+        _say(f"stats {st}")
+        assert info == 0
+        assert_schur(H, T, Q, w, tag=f"reorder{n}_{seed}")
+        total += st["reordering_windows"]
+    assert total > 0
 
 
 @pytest.mark.parametrize("nsmall", [8, 16])
