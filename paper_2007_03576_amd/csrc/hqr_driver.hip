@@ -623,12 +623,13 @@ int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd
     double *T = W.wT[depth], *Vw = W.wV[depth], *Ut = W.wU[depth];
     CK(launch_window_copy(V.H, V.ld, kwtop, w, T, w, Vw, w, C.hi));
     // Reading for the recursive solve of the window: AED windows of w/4
-    // (48..96, within the one-workgroup solver) with nw/4 shifts per sweep;
-    // the one-workgroup AED steps then converge the window with few sweeps.
+    // (48..96, within the one-workgroup solver) and as many shifts per sweep
+    // as such a window delivers (at most w/4).  Measured at n = 16384 (AED
+    // windows of 1024): nw/4 shifts 48.8 s per solve, 64 shifts 29.7 s, nw
+    // shifts 27.3 s; at n = 4096 (windows of 256) no difference.
     Params Pi = C.P;
-    auto_ns_nw(w, Pi.ns, Pi.nw);
     Pi.nw = std::min(std::max(w / 4, 48), MMAX);
-    Pi.ns = std::max(2, std::min(Pi.ns, (Pi.nw / 4) & ~1));
+    Pi.ns = std::max(2, Pi.nw & ~1);
     if (C.P.aed_nw > 0) Pi.nw = C.P.aed_nw;
     if (C.P.aed_ns > 0) Pi.ns = C.P.aed_ns;
     if (C.P.aed_nmin > 0) Pi.nmin = C.P.aed_nmin;
