@@ -68,12 +68,13 @@ def measured_traffic(kernel):
 
 def batched_run(seed):
     """Batched form: 20000 Gaussian Hessenberg matrices with orders drawn from
-    16..256, packed, T and Q for each.  The launch shape of the global grid
-    comes from the autotuner (its own seeded sample of orders 97..256); the
+    16..256, packed, T and Q for each.  The per-bucket AED window and shift
+    count (orders 97..128, 129..192, 193..256) and the launch shape of the
+    global grid come from the autotuners (their own seeded samples); the
     solve (order sort, two persistent grids draining a longest-first queue)
-    is captured once into a HIP graph and the second of two replays is timed.  The plain solver (one hqr_schur
-    call per matrix) is timed on a seeded sample of 64 matrices of the same
-    batch for comparison."""
+    is captured once into a HIP graph and the second of two replays is timed.
+    The plain solver (one hqr_schur call per matrix) is timed on a seeded
+    sample of 64 matrices of the same batch for comparison."""
     import numpy as np
     import torch
     import hqr_inputs as hi
@@ -85,6 +86,7 @@ def batched_run(seed):
     H0 = torch.from_numpy(packed).to(dev)
     from paper_2007_03576_amd import autotune
     t0 = time.perf_counter()
+    table = autotune.tune_table(seed=seed + 7)  # per-bucket (nw, ns), own seeded samples
     shape = autotune.tune(97, 256, seed=seed + 1)  # the global grid's orders, own seeded sample
     tune_s = time.perf_counter() - t0
     g = hq.BatchedGraph([int(n) for n in sizes])
@@ -123,6 +125,8 @@ def batched_run(seed):
             "s": dt, "solves_per_s": count / dt, "info_max": info_max,
             "accuracy_sample32": {"backward_rel_max": worst_be, "orth_max": worst_orth},
             "launch_shape": {"wg_per_cu": shape["wg_per_cu"], "wide_n": shape["wide_n"], "tune_s": tune_s},
+            "bucket_table": {"upper": table["upper"], "nw": table["nw"], "ns": table["ns"],
+                             "seconds": table["seconds"]},
             "plain_per_matrix": {"sample": "64 matrices of the batch, one hqr_schur call each",
                                  "solves_per_s": plain_rate},
             "speedup_vs_plain": (count / dt) / plain_rate}
@@ -137,7 +141,8 @@ def grad_run(seed):
     import paper_2007_03576_amd as hq
     from paper_2007_03576_amd import autotune
     H, _ = hi.prescribed_batch_device(512, 512, seed=seed, device="cuda")
-    # launch shape for 512 matrices of order 512 (candidates that differ at this order)
+    # AED window / shifts and launch shape for 512 matrices of order 512
+    table = autotune.tune_table(buckets=((512, 512),), count=512, seed=seed + 9)
     shape = autotune.tune(512, 512, count=512, seed=seed + 3,
                           candidates=((1, 4095), (2, 4095), (2, 320), (3, 320), (4, 320)))
     fw = bw = None
@@ -184,6 +189,7 @@ def grad_run(seed):
             "forward_s": fw, "backward_s": bw, "solves_per_s": 512 / (fw + bw),
             "accuracy_fd": {"h": h, "directions": fd_checks},
             "launch_shape": {"wg_per_cu": shape["wg_per_cu"], "wide_n": shape["wide_n"]},
+            "bucket_table": {"nw": table["nw"], "ns": table["ns"], "seconds": table["seconds"]},
             "plain_per_matrix": {"sample": "8 of the matrices, one hqr_schur call each, forward only",
                                  "solves_per_s": plain_rate},
             "speedup_vs_plain": (512 / (fw + bw)) / plain_rate}

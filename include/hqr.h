@@ -114,8 +114,10 @@ int hqr_schur_ex(double *H, double *Q, int64_t n, int64_t ld, double *wr, double
  * then LDS tier) take matrices from that queue one at a time, longest first;
  * orders above a threshold go to half of the global grid only (cache
  * footprint; see hqr_set_batched_launch).
- * Every order runs double-shift steps (hqr_params.small_shifts does not
- * apply here).  Matrices of order 0 get info 0 and are not touched.
+ * Orders <= 96 run double-shift steps; larger orders follow the per-bucket
+ * table of hqr_set_batched_table (AED window and shifts, default double
+ * shifts); hqr_params does not apply here.  Matrices of order 0 get info 0
+ * and are not touched.
  * Eigenvalues of matrix i go to wr/wi + eig_offsets[i]; info[i] receives the
  * per-matrix code (0 or +i).  offsets, n, eig_offsets, info are device
  * arrays.  Asynchronous on `stream`.  The queue lives in a buffer the library
@@ -151,6 +153,23 @@ int hqr_schur_batched_noalloc(double *H, double *Q, const int64_t *offsets, cons
 int hqr_set_batched_launch(int32_t wg_per_cu, int32_t wide_n);
 /* Current values (host pointers); returns 0, or -1 for a NULL pointer. */
 int hqr_get_batched_launch(int32_t *wg_per_cu, int32_t *wide_n);
+
+/* Per-size-bucket parameters of the batched form for orders above 96 (AED,
+ * Sec. 2.5; shifts per step, Sec. 2.3): bucket i (0 <= i < nb <= 8) holds the
+ * orders up to upper[i] (strictly increasing; the last bucket also takes
+ * every larger order).  nw[i] = 0 runs double-shift Francis for the bucket;
+ * otherwise nw[i] (8..64) is the AED window, held in LDS with its factor
+ * while H and Q stay in global memory, and ns[i] (even, 2..64) the number of
+ * undeflated candidates nearest the bottom used as shifts after each AED
+ * step, in ns[i]/2 double-shift sweeps (in exact arithmetic one sweep with a
+ * chain of ns[i]/2 bulges).  Active blocks of order <= 75, or after three AED
+ * steps without a deflation, finish with double shifts.  nb = 0 (default)
+ * restores double shifts for every order.  The package's autotuner picks the
+ * table by timing candidates per bucket; applies to later hqr_schur_batched
+ * calls.  Returns 0, -1 bad nb, -2 bad upper, -3 bad nw, -4 bad ns. */
+int hqr_set_batched_table(int32_t nb, const int32_t *upper, const int32_t *nw, const int32_t *ns);
+/* Current table (host arrays of 8 entries); returns 0, or -1 for a NULL pointer. */
+int hqr_get_batched_table(int32_t *nb, int32_t *upper, int32_t *nw, int32_t *ns);
 
 /* Right eigenvectors of H = Q T Q^T from its real Schur form, the phase after
  * the Schur reduction (Sec. 1: the eigenvectors of H are Q times those of

@@ -9,6 +9,7 @@ import torch
 from ._lib import HqrError, HqrParams, check, lib
 
 __all__ = ["schur", "schur_colmajor", "schur_batched", "eigvals", "hessenberg", "eigenvectors", "set_params", "params",
+           "set_batched_table", "batched_table",
            "last_stats", "HqrError", "BatchedProblem", "BatchedGraph", "set_batched_launch",
            "batched_launch"]
 
@@ -144,6 +145,24 @@ def eigenvectors(T: torch.Tensor, Q: torch.Tensor, w: torch.Tensor, stream=None)
 def set_batched_launch(wg_per_cu: int, wide_n: int) -> None:
     """Launch shape of the batched global-memory grid (hqr_set_batched_launch)."""
     check(lib().hqr_set_batched_launch(int(wg_per_cu), int(wide_n)), "hqr_set_batched_launch")
+
+
+def set_batched_table(upper: Sequence[int], nw: Sequence[int], ns: Sequence[int]) -> None:
+    """Per-size-bucket AED window nw and shifts per step ns of the batched
+    form for orders above 96 (hqr_set_batched_table): bucket i takes the
+    orders up to upper[i]; nw = 0 selects double-shift Francis.  Empty
+    sequences restore double shifts everywhere."""
+    k = len(upper)
+    arr = lambda v: (ctypes.c_int32 * max(k, 1))(*[int(x) for x in v])
+    check(lib().hqr_set_batched_table(k, arr(upper), arr(nw), arr(ns)), "hqr_set_batched_table")
+
+
+def batched_table() -> dict:
+    n = ctypes.c_int32()
+    u, w, s = (ctypes.c_int32 * 8)(), (ctypes.c_int32 * 8)(), (ctypes.c_int32 * 8)()
+    check(lib().hqr_get_batched_table(ctypes.byref(n), u, w, s), "hqr_get_batched_table")
+    k = n.value
+    return {"upper": list(u)[:k], "nw": list(w)[:k], "ns": list(s)[:k]}
 
 
 def batched_launch() -> dict:

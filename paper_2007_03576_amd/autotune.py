@@ -67,3 +67,52 @@ def tune(lo: int, hi: int, count: int = 0, seed: int = 7, device="cuda",
     if apply:
         api.set_batched_launch(wg, wide)
     return {"wg_per_cu": wg, "wide_n": wide, "seconds": {f"{a},{b}": t for (a, b), t in times.items()}}
+
+
+# Per-bucket AED window and shift count of the batched form (orders above
+# 96).  (0, 0) is double-shift Francis; the others are (nw, ns) pairs with the
+# window held in LDS (nw <= 64) and ns candidates used as shifts per step.
+TABLE_CANDIDATES: Tuple[Tuple[int, int], ...] = ((0, 0), (24, 12), (32, 16), (32, 32), (48, 24), (48, 48),
+                                                 (64, 32), (64, 64))
+BUCKETS: Tuple[Tuple[int, int], ...] = ((97, 128), (129, 192), (193, 256))
+
+
+def tune_table(buckets: Sequence[Tuple[int, int]] = BUCKETS, count: int = 0, seed: int = 11, device="cuda",
+               candidates: Sequence[Tuple[int, int]] = TABLE_CANDIDATES, reps: int = 1,
+               apply: bool = True) -> Dict:
+    """Times hqr_schur_batched on a seeded sample of each size bucket (orders
+    uniform in the bucket, `count` matrices, default two per CU) for every
+    (nw, ns) candidate and keeps the fastest whose solves all succeeded; the
+    last bucket also takes every larger order.  Returns {"upper", "nw", "ns",
+    "seconds": {bucket: {candidate: s}}} and installs the table if apply."""
+    dev = torch.device(device)
+    if count <= 0:
+        count = 2 * torch.cuda.get_device_properties(dev).multi_processor_count
+    prev = api.batched_table()
+    chosen_nw, chosen_ns, upper, secs = [], [], [], {}
+    try:
+        for bi, (lo, hi) in enumerate(buckets):
+            sizes, packed = sample(lo, hi, count, seed + bi, dev)
+            prob = api.BatchedProblem(sizes, True, dev)
+            times = {}
+            for nw, ns in candidates:
+                api.set_batched_table([4095], [nw], [ns])
+                best = float("inf")
+                for _ in range(reps):
+                    prob.load(packed)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    prob.solve()
+                    torch.cuda.synchronize()
+                    best = min(best, time.perf_counter() - t0)
+                times[(nw, ns)] = best if int(prob.info.abs().max()) == 0 else float("inf")
+            nw, ns = min(times, key=times.get)
+            chosen_nw.append(nw)
+            chosen_ns.append(ns)
+            upper.append(hi if bi + 1 < len(buckets) else 4095)
+            secs[f"{lo}-{hi}"] = {f"{a},{b}": t for (a, b), t in times.items()}
+    finally:
+        api.set_batched_table(prev["upper"], prev["nw"], prev["ns"])
+    if apply:
+        api.set_batched_table(upper, chosen_nw, chosen_ns)
+    return {"upper": upper, "nw": chosen_nw, "ns": chosen_ns, "seconds": secs}

@@ -141,9 +141,19 @@ hipError_t launch_transpose_pad(const double *V, int64_t ldv, int K, double *Ut,
 // Work queue of the batched form: QHDR header ints, then the matrix indices
 // in order of decreasing order n (longest first).
 constexpr int QHDR = 8;
+// Per-size-bucket parameters of the batched form: bucket i holds the orders
+// up to upper[i] (ascending; the last bucket takes every larger order); nw[i]
+// is its AED window (0: double-shift Francis only; at most BWIN) and ns[i] the
+// shifts per AED step.  Buckets apply to the orders above the LDS limit.
+constexpr int BWIN = 64;
+constexpr int MAXBUCKET = 8;
+struct BatchedTable {
+    int nb;
+    int upper[MAXBUCKET], nw[MAXBUCKET], ns[MAXBUCKET];
+};
 hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch,
                           double *wr, double *wi, const int64_t *eoff, int32_t *info, int32_t *queue,
-                          int wg_per_cu, int wide_n, hipStream_t s);
+                          int wg_per_cu, int wide_n, const BatchedTable &tab, hipStream_t s);
 // Backward pass of the eigenvalues (hqr_grad.hip): one descriptor per matrix
 // (offsets in doubles of T_b/Q_b/dH_b, of its eigenvalue slots, of its
 // workspace from the chunk's base -- 10 n^2 + 1 doubles -- and its order).

@@ -66,6 +66,9 @@ std::map<std::pair<int, void *>, BwdWs> g_bwd;
 // for three rows, three columns of H and Q); two workgroups per CU keep that
 // inside the CU's share of L2 (4 MB per 32 CUs) up to about n = 360.
 int g_batched_wg_per_cu = 2, g_batched_wide_n = 320;
+// Per-bucket AED window and shift count of the batched form (empty: double
+// shifts for every order), chosen by the package's autotuner.
+BatchedTable g_btab = {0, {0}, {0}, {0}};
 constexpr int NSTATS = 10;
 thread_local int64_t t_stats[NSTATS];
 
@@ -1250,10 +1253,12 @@ int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_
     if (!info) return -9;
     int32_t *queue = nullptr;
     int wg_per_cu, wide_n;
+    BatchedTable tab;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         wg_per_cu = g_batched_wg_per_cu;
         wide_n = g_batched_wide_n;
+        tab = g_btab;
         int dev = 0;
         CK(hipGetDevice(&dev));
         QueueBuf &qb = g_queues[std::make_pair(dev, stream)];
@@ -1270,7 +1275,7 @@ int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_
         }
         queue = qb.p;
     }
-    CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, queue, wg_per_cu, wide_n,
+    CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, queue, wg_per_cu, wide_n, tab,
                       (hipStream_t)stream));
     return 0;
 }
@@ -1308,6 +1313,7 @@ int hqr_schur_batched_noalloc(double *H, double *Q, const int64_t *offsets, cons
     if (dev < 0 || dev >= 16) return -1000;
     int32_t *queue;
     int wg_per_cu, wide_n;
+    BatchedTable tab;
     {
         std::lock_guard<std::mutex> lk(g_scratch_mu);
         if (!g_scratch_ptr[dev]) {
@@ -1321,10 +1327,11 @@ int hqr_schur_batched_noalloc(double *H, double *Q, const int64_t *offsets, cons
         std::lock_guard<std::mutex> lk(g_mu);
         wg_per_cu = g_batched_wg_per_cu;
         wide_n = g_batched_wide_n;
+        tab = g_btab;
     }
     // the sort kernel writes every queue head and position it uses, so the
     // array needs no clearing between calls
-    CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, queue, wg_per_cu, wide_n,
+    CK(launch_batched(H, Q, offsets, n, batch, wr, wi, eig_offsets, info, queue, wg_per_cu, wide_n, tab,
                       (hipStream_t)stream));
     return 0;
 }
@@ -1336,6 +1343,38 @@ int hqr_set_batched_launch(int32_t wg_per_cu, int32_t wide_n)
     std::lock_guard<std::mutex> lk(g_mu);
     g_batched_wg_per_cu = wg_per_cu;
     g_batched_wide_n = wide_n;
+    return 0;
+}
+
+int hqr_set_batched_table(int32_t nb, const int32_t *upper, const int32_t *nw, const int32_t *ns)
+{
+    if (nb < 0 || nb > MAXBUCKET) return -1;
+    if (nb > 0 && (!upper || !nw || !ns)) return -2;
+    BatchedTable t = {0, {0}, {0}, {0}};
+    for (int i = 0; i < nb; ++i) {
+        if (upper[i] < 1 || (i > 0 && upper[i] <= upper[i - 1])) return -2;
+        if (nw[i] != 0 && (nw[i] < 8 || nw[i] > BWIN)) return -3;
+        if (ns[i] < 0 || (ns[i] & 1) || (nw[i] != 0 && ns[i] < 2) || ns[i] > BWIN) return -4;
+        t.upper[i] = upper[i];
+        t.nw[i] = nw[i];
+        t.ns[i] = ns[i];
+    }
+    t.nb = nb;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_btab = t;
+    return 0;
+}
+
+int hqr_get_batched_table(int32_t *nb, int32_t *upper, int32_t *nw, int32_t *ns)
+{
+    if (!nb || !upper || !nw || !ns) return -1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    *nb = g_btab.nb;
+    for (int i = 0; i < MAXBUCKET; ++i) {
+        upper[i] = g_btab.upper[i];
+        nw[i] = g_btab.nw[i];
+        ns[i] = g_btab.ns[i];
+    }
     return 0;
 }
 

@@ -29,6 +29,10 @@ int update_tile(int K16, int side)
     return t;
 }
 
+// Output strips of 16 per wave item, and wave items per workgroup.
+constexpr int SG = 6;
+constexpr int UPD_WAVES = UPD_THREADS / 64;
+
 __global__ void __launch_bounds__(UPD_THREADS) k_update(UpdBatch B)
 {
     extern __shared__ __align__(16) double Pt[];
@@ -64,15 +68,16 @@ __global__ void __launch_bounds__(UPD_THREADS) k_update(UpdBatch B)
     __syncthreads();
     // work items: (panel tile of 16 rows/columns, group of up to SG output
     // strips of 16); with K <= 96 the four waves take one panel tile each and
-    // every strip, so they carry equal MFMA work
-    constexpr int SG = 6;
+    // every strip, so they carry equal MFMA work.  The update is in place, so
+    // the whole K-long panel of a tile belongs to one workgroup: it reads all
+    // of it before it writes any output.
     const int lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
     const int ntj = K16 / 16;
     const int nta = (cnt + 15) / 16;
     const int ngrp = (ntj + SG - 1) / SG;
     const double *Ut = J.Ut;
-    for (int item = wave; item < nta * ngrp; item += UPD_THREADS / 64) {
+    for (int item = wave; item < nta * ngrp; item += UPD_WAVES) {
         const int at = item % nta, j0 = (item / nta) * SG;
         const int nj = min(SG, ntj - j0);
         dbl4 acc[SG];

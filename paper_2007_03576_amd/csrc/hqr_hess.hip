@@ -17,7 +17,7 @@
 //     panel's first j reflectors act on it); its reflector extends V and T,
 //     and y_j = A0 v_j is a matrix-vector product over all rows (k_hh_gemv,
 //     many workgroups, partial sums per column chunk) that the next column's
-//     kernel folds into Y (k_hh_col, one workgroup of 1024 threads);
+//     kernel folds into Y (k_hh_col, one workgroup of 512 threads);
 //   * after the panel: A <- Q_p^T (A0 - Y V^T) on the columns right of the
 //     panel (extra columns R included in the left product) and Z <- Z Q_p,
 //     as FP64-MFMA matrix products (k_hh_gemm).
@@ -30,7 +30,7 @@ namespace hqr {
 
 typedef double dbl4h __attribute__((ext_vector_type(4)));
 
-constexpr int HT = 1024; // threads of the panel-column kernel
+constexpr int HT = 512; // threads of the panel-column kernel (register budget 256)
 
 // Sum of `cnt` per-thread partial values (cnt <= NBH) over the workgroup;
 // every thread receives all sums in out[] (LDS scratch red: 16 x NBH).
@@ -92,17 +92,26 @@ __global__ void __launch_bounds__(HT) k_hh_col(double *A, int64_t lda, int m, in
     __shared__ double red[16 * NBH];
     __shared__ double sv[NBH];
     __shared__ double sv2[NBH];
+    __shared__ double sT[NBH * NBH]; // T(:, :j) of the panel, read by the small triangular products
     const int tid = threadIdx.x;
     const int64_t ldm = m;
     if (j > 0) {
         const int jp = j - 1;
         const double tp = tau[jp];
+        // loops over static bounds with predicates, so the loads of a row
+        // are all in flight at once instead of one latency per term
         for (int r = tid; r < m; r += HT) {
-            double y = 0.0;
-            for (int q = 0; q < nchunk; ++q) y += part[(int64_t)q * m + r];
+            double y0 = 0.0, y1 = 0.0;
+#pragma unroll 8
+            for (int q = 0; q < nchunk; q += 2) {
+                y0 += part[(int64_t)q * m + r];
+                if (q + 1 < nchunk) y1 += part[(int64_t)(q + 1) * m + r];
+            }
             double s = 0.0;
-            for (int i = 0; i < jp; ++i) s += Y[r + i * ldm] * W[i + jp * NBH];
-            Y[r + jp * ldm] = tp * (y - s);
+#pragma unroll
+            for (int i = 0; i < NBH; ++i)
+                if (i < jp) s += Y[r + i * ldm] * W[i + jp * NBH];
+            Y[r + jp * ldm] = tp * ((y0 + y1) - s);
         }
         __syncthreads();
     }
@@ -110,6 +119,7 @@ __global__ void __launch_bounds__(HT) k_hh_col(double *A, int64_t lda, int m, in
     const int c = k + j;
     // x = A0(:, c) - Y(:, :j) V(c, :j)^T ; kept in V(:, j) as scratch until the reflector is known
     if (tid < j) sv[tid] = V[c + tid * ldm];
+    for (int it = tid; it < NBH * j; it += HT) sT[it] = Tm[it];
     __syncthreads();
     double *x = V + (int64_t)j * ldm;
     double loc[NBH];
@@ -117,7 +127,9 @@ __global__ void __launch_bounds__(HT) k_hh_col(double *A, int64_t lda, int m, in
     for (int i = 0; i < NBH; ++i) loc[i] = 0.0;
     for (int r = tid; r < m; r += HT) {
         double v = A[r + (int64_t)c * lda];
-        for (int i = 0; i < j; ++i) v -= Y[r + i * ldm] * sv[i];
+#pragma unroll
+        for (int i = 0; i < NBH; ++i)
+            if (i < j) v -= Y[r + i * ldm] * sv[i];
         x[r] = v;
         if (r >= k + 1) {
 #pragma unroll
@@ -127,18 +139,20 @@ __global__ void __launch_bounds__(HT) k_hh_col(double *A, int64_t lda, int m, in
     }
     // x(k+1:) <- Q_{j-1}^T x = x - V T^T (V^T x)
     hh_multi_sum(loc, j, red, sv);
-    if (tid == 0)
-        for (int i = 0; i < j; ++i) {
-            double t = 0.0;
-            for (int l = 0; l <= i; ++l) t += Tm[l + i * NBH] * sv[l]; // (T^T s)_i = sum_l T(l, i) s_l
-            sv2[i] = t;
-        }
+    if (tid < j) { // (T^T s)_i = sum_{l <= i} T(l, i) s_l, one thread per i
+        double t = 0.0;
+        for (int l = 0; l <= tid; ++l) t += sT[l + tid * NBH] * sv[l];
+        sv2[tid] = t;
+    }
     __syncthreads();
     double amax = 0.0;
     for (int r = tid; r < m; r += HT) {
         double v = x[r];
-        if (r >= k + 1)
-            for (int i = 0; i < j; ++i) v -= V[r + i * ldm] * sv2[i];
+        if (r >= k + 1) {
+#pragma unroll
+            for (int i = 0; i < NBH; ++i)
+                if (i < j) v -= V[r + i * ldm] * sv2[i];
+        }
         x[r] = v;
         if (r <= c) A[r + (int64_t)c * lda] = v; // final rows 0..c of column c
         if (r >= c + 2) amax = fmax(amax, fabs(v));
@@ -177,18 +191,15 @@ __global__ void __launch_bounds__(HT) k_hh_col(double *A, int64_t lda, int m, in
         }
     }
     hh_multi_sum(loc, j, red, sv);
-    if (tid == 0) {
-        for (int i = 0; i < j; ++i) W[i + j * NBH] = sv[i];
-        // T(:j, j) = -tau_j T(:j, :j) w_j
-        for (int i = 0; i < j; ++i) {
-            double t = 0.0;
-            for (int l = i; l < j; ++l) t += Tm[i + l * NBH] * sv[l];
-            Tm[i + j * NBH] = -tj * t;
-        }
-        Tm[j + j * NBH] = tj;
-        for (int i = j + 1; i < NBH; ++i) Tm[i + j * NBH] = 0.0;
-        tau[j] = tj;
+    if (tid < j) { // T(:j, j) = -tau_j T(:j, :j) w_j, one thread per row
+        W[tid + j * NBH] = sv[tid];
+        double t = 0.0;
+        for (int l = tid; l < j; ++l) t += sT[tid + l * NBH] * sv[l];
+        Tm[tid + j * NBH] = -tj * t;
+    } else if (tid < NBH) {
+        Tm[tid + j * NBH] = (tid == j) ? tj : 0.0;
     }
+    if (tid == 0) tau[j] = tj;
 }
 
 // Partial sums of y = A(:, c+1:m) v(c+1:m) for column chunks: grid (row

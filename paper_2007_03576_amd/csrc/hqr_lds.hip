@@ -1027,17 +1027,19 @@ __device__ __forceinline__ void ds_step(SmemCore &S, double *A, int lda, int m, 
 
 // Francis double-shift QR on the whole matrix A (order m, full T), Z accumulates.
 // Returns 0 or 1 + the bottom row of the block that did not converge.
+// Rows ilo..ihi only when given (ihi < 0: the whole matrix); the updates
+// still cover the full rows and columns of the order-m matrix.
 __device__ __forceinline__ int qr_ds(SmemCore &S, double *A, int lda, int m, double *Z, int ldz, int nz, const Defl &dfl,
-                     int64_t itmax_in)
+                     int64_t itmax_in, int ilo = 0, int ihi = -1)
 {
     int64_t itmax = 30 * (int64_t)max(10, m);
     if (itmax_in > 0 && itmax_in < itmax) itmax = itmax_in;
     int64_t total = 0;
-    int i = m - 1;
-    while (i >= 0) {
+    int i = (ihi < 0) ? m - 1 : ihi;
+    while (i >= ilo) {
         int its = 0, l;
         for (;;) {
-            l = find_split(S, A, lda, 0, i, dfl);
+            l = find_split(S, A, lda, ilo, i, dfl);
             if (l >= i - 1) break;
             if (total >= itmax) return i + 1;
             ds_step(S, A, lda, m, Z, ldz, nz, l, i, its);
@@ -1747,7 +1749,8 @@ __device__ __forceinline__ void axpy_v(double a, const double *v, double *x, int
 
 // Householder vector of x = vec[0..len-1] (in LDS): overwrites vec with v
 // (v[0] = 1) and returns tau; beta in S.sc[2].
-__device__ __forceinline__ double house_vec(Smem &S, double *vec, int len)
+template <class SM>
+__device__ __forceinline__ double house_vec(SM &S, double *vec, int len)
 {
     double amax = 0.0;
     for (int i = 1 + (int)threadIdx.x; i < len; i += NT) amax = fmax(amax, fabs(vec[i]));
@@ -1781,7 +1784,8 @@ __device__ __forceinline__ double house_vec(Smem &S, double *vec, int len)
 // Spike removal and Householder Hessenberg reduction of T(0:ns,0:ns) in LDS;
 // the reflectors also update T(0:ns, ns:nt) and Z (nz rows).  The spike is
 // spscale * Z[sprow, 0:ns] on entry.  Returns the new subdiagonal entry.
-__device__ __forceinline__ double restore_lds(Smem &S, double *T, int ldt, int nt, int ns, double *Z, int ldz, int nz,
+template <class SM>
+__device__ __forceinline__ double restore_lds(SM &S, double *T, int ldt, int nt, int ns, double *Z, int ldz, int nz,
                               int sprow, double spscale)
 {
     double *v = S.vec;
@@ -2733,9 +2737,260 @@ __global__ void __launch_bounds__(NT) k_batched_global(double *H, double *Q, con
     }
 }
 
+// ---------------------------------------------------------------------------
+// batched form with aggressive early deflation (orders above the LDS limit):
+// H and Q stay in global memory, an LDS window of order <= BWIN holds the AED
+// window and its factor.  Per matrix and size bucket: AED window nw and
+// shifts per step ns (Sec. 2.5); the ns undeflated candidates nearest the
+// bottom are used as ns/2 successive double-shift sweeps, which in exact
+// arithmetic equal one sweep with a chain of ns/2 bulges (Sec. 2.3, implicit
+// Q theorem).
+
+constexpr int LDB = BWIN + 1;
+constexpr int BNMIN = 75; // active blocks of at most this order finish with double shifts
+struct SmemB : SmemCore {
+    double A[BWIN * LDB];
+    double Z[LDB * LDB];
+    double vec[LDB];
+    double cr[BWIN], ci[BWIN]; // candidate eigenvalues of the AED window
+    double pr[BWIN], pi[BWIN]; // the shifts of the next sweeps, paired
+};
+static_assert(2 * sizeof(SmemB) <= 160 * 1024, "two AED workgroups per CU");
+
+// X(0:rows, 0:nw) <- X Z for a panel in global memory (leading dimension ldx),
+// row chunks staged through the LDS buffer buf (BWIN x LDB).
+__device__ void bw_right(double *X, int64_t ldx, int rows, int nw, const double *Z, double *buf)
+{
+    for (int r0 = 0; r0 < rows; r0 += BWIN) {
+        const int rc = min(BWIN, rows - r0);
+        for (int it = threadIdx.x; it < rc * nw; it += NT) {
+            const int r = it % rc, k = it / rc;
+            buf[r + k * LDB] = X[(r0 + r) + (int64_t)k * ldx];
+        }
+        __syncthreads();
+        for (int it = threadIdx.x; it < rc * nw; it += NT) {
+            const int r = it % rc, j = it / rc;
+            double a0 = 0.0, a1 = 0.0;
+            int k = 0;
+            for (; k + 1 < nw; k += 2) {
+                a0 += buf[r + k * LDB] * Z[k + j * LDB];
+                a1 += buf[r + (k + 1) * LDB] * Z[(k + 1) + j * LDB];
+            }
+            if (k < nw) a0 += buf[r + k * LDB] * Z[k + j * LDB];
+            X[(r0 + r) + (int64_t)j * ldx] = a0 + a1;
+        }
+        __syncthreads();
+    }
+}
+
+// X(0:nw, 0:cols) <- Z^T X for a panel in global memory.
+__device__ void bw_left(double *X, int64_t ldx, int cols, int nw, const double *Z, double *buf)
+{
+    for (int c0 = 0; c0 < cols; c0 += BWIN) {
+        const int cc = min(BWIN, cols - c0);
+        for (int it = threadIdx.x; it < cc * nw; it += NT) {
+            const int k = it % nw, c = it / nw;
+            buf[k + c * LDB] = X[k + (int64_t)(c0 + c) * ldx];
+        }
+        __syncthreads();
+        for (int it = threadIdx.x; it < cc * nw; it += NT) {
+            const int j = it % nw, c = it / nw;
+            double a0 = 0.0, a1 = 0.0;
+            int k = 0;
+            for (; k + 1 < nw; k += 2) {
+                a0 += Z[k + j * LDB] * buf[k + c * LDB];
+                a1 += Z[(k + 1) + j * LDB] * buf[(k + 1) + c * LDB];
+            }
+            if (k < nw) a0 += Z[k + j * LDB] * buf[k + c * LDB];
+            X[j + (int64_t)(c0 + c) * ldx] = a0 + a1;
+        }
+        __syncthreads();
+    }
+}
+
+// One matrix of order n (leading dimension n) in global memory, Q (may be
+// NULL) accumulated: AED steps with window nwb and up to nsb shifts, double
+// shifts once the active block is small (or after three AED steps without a
+// deflation).  Returns 0 or the failure code of the small solver / the
+// iteration limit (1-based row).
+__device__ int batched_aed_solve(SmemB &S, double *A, int n, double *Q, int nwb, int nsb, const Defl &dfl)
+{
+    const int nz = Q ? n : 0;
+    double *Z = Q ? Q : A; // without Q: no Z rows (nz = 0)
+    const int64_t itmax = 30 * (int64_t)max(10, n);
+    int64_t iters = 0;
+    int kbot = n - 1, nodefl = 0;
+    while (kbot >= 0) {
+        const int ktop = find_split(S, A, n, 0, kbot, dfl);
+        const int nh = kbot - ktop + 1;
+        if (nh <= BNMIN || nodefl >= 3) {
+            const int inf = qr_ds(S, A, n, n, Z, n, nz, dfl, 0, ktop, kbot);
+            if (inf > 0) return inf;
+            kbot = ktop - 1;
+            nodefl = 0;
+            continue;
+        }
+        if (++iters > itmax) return kbot + 1;
+        const int nw = min(nwb, nh);
+        const int kw = kbot - nw + 1;
+        const double s = (kw > ktop) ? A[kw + (int64_t)(kw - 1) * n] : 0.0;
+        for (int it = threadIdx.x; it < nw * nw; it += NT) {
+            const int r = it % nw, c = it / nw;
+            S.A[r + c * LDB] = (r <= c + 1) ? A[(kw + r) + (int64_t)(kw + c) * n] : 0.0;
+        }
+        identity_lds(S.Z, LDB, nw, nw);
+        __syncthreads();
+        const int winf = qr_ds(S, S.A, LDB, nw, S.Z, LDB, nw, dfl, 0);
+        const int ns = aed_deflate(S, S.A, LDB, nw, S.Z, LDB, nw, 0, s, winf > 0 ? winf : 0, dfl);
+        const int nd = nw - ns;
+        if (threadIdx.x == 0) {
+            // candidates: eigenvalues of the undeflated blocks in diagonal order
+            int k = 0;
+            while (k < ns) {
+                const int sz = (k + 1 < ns && S.A[(k + 1) + k * LDB] != 0.0) ? 2 : 1;
+                if (sz == 1) {
+                    S.cr[k] = S.A[k + k * LDB];
+                    S.ci[k] = 0.0;
+                } else {
+                    double r1, i1, r2, i2;
+                    eig2x2(S.A[k + k * LDB], S.A[k + (k + 1) * LDB], S.A[(k + 1) + k * LDB],
+                           S.A[(k + 1) + (k + 1) * LDB], r1, i1, r2, i2);
+                    if (i1 < 0.0) {
+                        const double t = i1;
+                        i1 = i2;
+                        i2 = t;
+                    }
+                    S.cr[k] = r1;
+                    S.ci[k] = i1;
+                    S.cr[k + 1] = r2;
+                    S.ci[k + 1] = i2;
+                }
+                k += sz;
+            }
+            // the bottommost min(nsb, ns) candidates, conjugate pairs together,
+            // real ones paired in order, an odd real one left over dropped
+            const int want = min(nsb, ns);
+            int start = ns - want;
+            if (start > 0 && start < ns && S.ci[start] < 0.0) start++;
+            int nsh = 0, nr = 0;
+            double rr = 0.0;
+            for (int i = ns - 1; i >= start; --i) {
+                if (S.ci[i] != 0.0) {
+                    if (S.ci[i] < 0.0 && i - 1 >= start) {
+                        S.pr[nsh] = S.cr[i - 1];
+                        S.pi[nsh] = S.ci[i - 1];
+                        S.pr[nsh + 1] = S.cr[i];
+                        S.pi[nsh + 1] = S.ci[i];
+                        nsh += 2;
+                        --i;
+                    }
+                } else if (nr == 0) {
+                    rr = S.cr[i];
+                    nr = 1;
+                } else {
+                    S.pr[nsh] = rr;
+                    S.pi[nsh] = 0.0;
+                    S.pr[nsh + 1] = S.cr[i];
+                    S.pi[nsh + 1] = 0.0;
+                    nsh += 2;
+                    nr = 0;
+                }
+            }
+            S.ic[5] = nsh;
+        }
+        __syncthreads();
+        const int nsh = S.ic[5];
+        if (nd > 0) {
+            double beta = 0.0;
+            if (ns >= 1) beta = s * S.Z[0];
+            if (ns > 1 && s != 0.0) beta = restore_lds(S, S.A, LDB, nw, ns, S.Z, LDB, nw, 0, s);
+            for (int it = threadIdx.x; it < nw * nw; it += NT) {
+                const int r = it % nw, c = it / nw;
+                A[(kw + r) + (int64_t)(kw + c) * n] = (r <= c + 1) ? S.A[r + c * LDB] : 0.0;
+            }
+            if (kw > ktop && threadIdx.x == 0) A[kw + (int64_t)(kw - 1) * n] = (ns >= 1) ? beta : 0.0;
+            __syncthreads();
+            // the window's factor on the rows above it, the columns right of
+            // the active block and Q (S.A is free now and stages the panels)
+            bw_right(A + (int64_t)kw * n, n, kw, nw, S.Z, S.A);
+            bw_left(A + kw + (int64_t)(kbot + 1) * n, n, n - kbot - 1, nw, S.Z, S.A);
+            if (Q) bw_right(Q + (int64_t)kw * n, n, n, nw, S.Z, S.A);
+            kbot -= nd;
+            nodefl = 0;
+            if (100 * nd > 14 * nw) continue; // many deflations: AED again
+        } else {
+            ++nodefl;
+        }
+        if (kbot - ktop + 1 <= BNMIN) continue;
+        for (int p = 0; p + 1 < nsh; p += 2) {
+            if (threadIdx.x == 0) {
+                S.sr[0] = S.pr[p];
+                S.si[0] = S.pi[p];
+                S.sr[1] = S.pr[p + 1];
+                S.si[1] = S.pi[p + 1];
+            }
+            __syncthreads();
+            chase_la(S, A, n, ktop, kbot, n - 1, Z, n, nz);
+        }
+    }
+    return 0;
+}
+
+// Orders above the LDS limit with a per-bucket (nw, ns) table: matrices of
+// buckets with an AED window solve with batched_aed_solve, the others with
+// double shifts as in k_batched_global.  Same work queue as k_batched_global.
+__global__ void __launch_bounds__(NT) k_batched_aed(double *H, double *Q, const int64_t *offs, const int32_t *nn,
+                                                    int batch, double *wr, double *wi, const int64_t *eoff,
+                                                    int32_t *info, int32_t *q, BatchedTable tab)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    SmemB &S = *reinterpret_cast<SmemB *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int32_t *order = q + QHDR;
+    const int nbig = q[2], nwide = q[5];
+    bool wide = blockIdx.x < (gridDim.x + 1) / 2 && nwide > 0;
+    for (;;) {
+        int k;
+        if (wide) {
+            k = queue_next(S, &q[0]);
+            if (k >= nwide) {
+                wide = false;
+                continue;
+            }
+        } else {
+            k = queue_next(S, &q[4]);
+            if (k >= nbig) break;
+        }
+        const int b = order[k];
+        const int n = nn[b];
+        double *A = H + offs[b];
+        for (int it = tid; it < n * n; it += NT) {
+            int r = it % n, c = it / n;
+            if (r > c + 1) A[it] = 0.0;
+        }
+        int bk = 0;
+        while (bk + 1 < tab.nb && n > tab.upper[bk]) ++bk;
+        const int nwb = min(tab.nw[bk], BWIN), nsb = tab.ns[bk] & ~1;
+        double *Qb = Q ? Q + offs[b] : nullptr;
+        __syncthreads();
+        const Defl dfl{DBL_MIN * ((double)n / kU), -1.0};
+        int inf;
+        if (nwb >= 8 && nsb >= 2)
+            inf = batched_aed_solve(S, A, n, Qb, nwb, nsb, dfl);
+        else
+            inf = qr_small(S, A, n, n, Qb ? Qb : A, n, Qb ? n : 0, dfl, 0, 2);
+        __syncthreads();
+        if (tid == 0) {
+            batched_eigs(A, n, n, wr + eoff[b], wi + eoff[b]);
+            info[b] = inf;
+        }
+        __syncthreads();
+    }
+}
+
 hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch, double *wr,
                           double *wi, const int64_t *eoff, int32_t *info, int32_t *queue, int wg_per_cu, int wide_n,
-                          hipStream_t s)
+                          const BatchedTable &tab, hipStream_t s)
 {
     hipError_t e = prep((const void *)k_batched);
     if (e != hipSuccess) return e;
@@ -2748,9 +3003,22 @@ hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const in
     hipLaunchKernelGGL(k_batched_order, dim3(1), dim3(QNT), 0, s, n, batch, wide_n, queue, info);
     // orders > MMAX first (they dominate the time), then the LDS tier; each
     // grid drains its queue longest-first
-    hipLaunchKernelGGL(k_batched_global, dim3(std::min(batch, wg_per_cu * ncu)), dim3(NT), 0, s, H, Q, offsets, n,
-                       batch,
-                       wr, wi, eoff, info, queue);
+    bool aed = false;
+    for (int i = 0; i < tab.nb; ++i) aed = aed || (tab.upper[i] > MMAX && tab.nw[i] >= 8 && tab.ns[i] >= 2);
+    if (aed) {
+        static bool attr = false;
+        if (!attr) {
+            e = hipFuncSetAttribute((const void *)k_batched_aed, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)sizeof(SmemB));
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_batched_aed, dim3(std::min(batch, wg_per_cu * ncu)), dim3(NT), sizeof(SmemB), s, H, Q,
+                           offsets, n, batch, wr, wi, eoff, info, queue, tab);
+    } else {
+        hipLaunchKernelGGL(k_batched_global, dim3(std::min(batch, wg_per_cu * ncu)), dim3(NT), 0, s, H, Q, offsets,
+                           n, batch, wr, wi, eoff, info, queue);
+    }
     hipLaunchKernelGGL(k_batched, dim3(std::min(batch, ncu)), dim3(NT), smem_bytes(), s, H, Q, offsets, n, batch,
                        wr, wi, eoff, info, queue);
     return hipGetLastError();

@@ -202,3 +202,41 @@ def test_autotune_launch_shape_installed_and_results_unchanged(gpu):
             assert torch.equal(H, outs[0][0]) and torch.equal(Q, outs[0][1])
     finally:
         hq.set_batched_launch(prev["wg_per_cu"], prev["wide_n"])
+
+
+@pytest.mark.parametrize("table", [
+    {"upper": [4095], "nw": [32], "ns": [16]},
+    {"upper": [128, 192, 4095], "nw": [24, 48, 64], "ns": [12, 24, 48]},
+    {"upper": [150, 4095], "nw": [0, 40], "ns": [0, 40]},
+])
+def test_batched_aed_table(gpu, table):
+    """Per-bucket AED windows and shift counts for orders above 96 (H and Q
+    in global memory, the AED window in LDS), mixed with double shifts below
+    and in buckets without AED; every matrix against the oracle."""
+    import torch
+    import paper_2007_03576_amd as hq
+    _say(f"case batched AED table {table}")
+    hq.set_batched_table(table["upper"], table["nw"], table["ns"])
+    try:
+        mats, _ = _packed_case(1, 260, 30, 17)
+        mats = mats[:10] + [np.zeros((0, 0))] + mats[10:]
+        dev = [torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in mats]
+        Ts, Qs, ws, info = hq.schur_batched(dev)
+        torch.cuda.synchronize()
+        info = info.cpu().numpy()
+        for i, H in enumerate(mats):
+            if H.shape[0] == 0:
+                assert info[i] == 0
+                continue
+            check_one(H, Ts[i].cpu().numpy(), Qs[i].cpu().numpy(), ws[i].cpu().numpy(), int(info[i]),
+                      f"t{i} n={H.shape[0]}")
+        # prescribed spectra through the AED path
+        for i, n in enumerate([120, 200, 256]):
+            H, ev = hi.prescribed_hessenberg(n, seed=900 + i)
+            Tl, Ql, wl, inf = hq.schur_batched([torch.from_numpy(np.ascontiguousarray(H)).cuda()])
+            w = wl[0].cpu().numpy()
+            _, _, d = checks.match(w, ev)
+            assert d.max() <= 1e-10 * np.linalg.norm(H)
+            check_one(H, Tl[0].cpu().numpy(), Ql[0].cpu().numpy(), w, int(inf[0]), f"p{n}")
+    finally:
+        hq.set_batched_table([], [], [])

@@ -119,6 +119,17 @@ def test_big_aed_reordering_chains(gpu):
     assert total > 0
 
 
+def test_large_window_factor(gpu):
+    # an AED window of 1024: its factor (order 1024) is applied by the update
+    # kernel with the whole 1024-long panel of each tile staged in LDS
+    _say("case AED window 1024 n=1300 ns=64")
+    H = hi.gaussian_hessenberg(1300, seed=31)
+    T, Q, w, info, st = run_gpu(H, {"ns": 64, "nw": 1024})
+    _say(f"stats {st}")
+    assert info == 0
+    assert_schur(H, T, Q, w, tag="win1024")
+
+
 @pytest.mark.parametrize("nsmall", [8, 16])
 @pytest.mark.parametrize("n,params", [(90, {}), (300, {"ns": 16, "nw": 80})])
 def test_multishift_small_solver(gpu, n, params, nsmall):
