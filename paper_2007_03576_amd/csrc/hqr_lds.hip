@@ -544,6 +544,46 @@ __device__ inline void house3c(int m, double x0, double x1, double x2, double &v
     }
 }
 
+// 1/sqrt(s) from the hardware estimate and two Newton steps, for s well
+// inside the normal range (within a few ulps).
+__device__ inline double rsq_nr(double s)
+{
+    double r = __builtin_amdgcn_rsq(s);
+    double t = s * r;
+    double e = fma(-t, r, 1.0);
+    r = fma(r * 0.5, e, r);
+    t = s * r;
+    e = fma(-t, r, 1.0);
+    return fma(r * 0.5, e, r);
+}
+
+// house3c with the norm from a reciprocal square root: tau = 1 + |x0|/||x||
+// needs no quotient, and the one reciprocal (of x0 - beta) gives v.  Shorter
+// dependency chain than a rounded square root followed by a reciprocal.
+__device__ inline void house3r(int m, double x0, double x1, double x2, double &v1, double &v2, double &tau,
+                               double &beta)
+{
+    const double t1 = (m > 1) ? x1 : 0.0, t2 = (m > 2) ? x2 : 0.0;
+    const double q = fma(t1, t1, t2 * t2);
+    const double ss = fma(x0, x0, q);
+    if (ss > 0x1p-900 && ss < 0x1p+900 && q > 0x1p-900) {
+        const double r = rsq_nr(ss);
+        const double nrm = ss * r;
+        const double b = (x0 >= 0.0) ? -nrm : nrm;
+        const double rd = rcp_nr(x0 - b);
+        tau = fma(fabs(x0), r, 1.0);
+        v1 = t1 * rd;
+        v2 = t2 * rd;
+        beta = b;
+    } else if (t1 == 0.0 && t2 == 0.0) {
+        tau = 0.0;
+        beta = x0;
+        v1 = v2 = 0.0;
+    } else {
+        house3(m, x0, x1, x2, v1, v2, tau, beta);
+    }
+}
+
 // Single-bulge chase (one double-shift sweep) through the matrix held in LDS:
 // the reflector at k acts on rows/columns k+1..k+m of the active block
 // [ktop,kbot] (indices global, local = global - off), left products on local
@@ -761,7 +801,7 @@ __device__ __forceinline__ void chase_la(SmemCore &S, double *A, int lda, int kt
             x2 = f * h32;
         }
         const int m0 = min(3, kb - kfirst);
-        house3c(m0, x0, x1, x2, cv1, cv2, ctau, cbeta);
+        house3r(m0, x0, x1, x2, cv1, cv2, ctau, cbeta);
         if (m0 < 3) cv2 = 0.0;
         if (lane == 0) {
             S.bv1[0] = cv1;
@@ -787,6 +827,8 @@ __device__ __forceinline__ void chase_la(SmemCore &S, double *A, int lda, int kt
             // 97..256; the same grouping costs 4 % per position in LDS).
             constexpr int SG = 8;
             if (__builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void *)A)) {
+                // stored back unconditionally (tau = 0 leaves the segment
+                // unchanged), so the segment's loads go out with the reflector's
                 for (int it = tid; it < nseg; it += NSEGT) {
                     const int r = it - ncL;
                     const bool isL = it < ncL, isA = !isL && r < nrR, isZ = !isL && !isA && r < nrR + nz;
@@ -797,12 +839,10 @@ __device__ __forceinline__ void chase_la(SmemCore &S, double *A, int lda, int kt
                     const int st = isL ? 1 : ldb;
                     double *p = base + prow + pcol * ldb;
                     double y0 = p[0], y1 = p[st], y2 = (m == 3) ? p[2 * st] : 0.0;
-                    if (tau != 0.0) {
-                        refl3(m, tau, v1, v2, y0, y1, y2);
-                        p[0] = y0;
-                        p[st] = y1;
-                        if (m == 3) p[2 * st] = y2;
-                    }
+                    refl3(m, tau, v1, v2, y0, y1, y2);
+                    p[0] = y0;
+                    p[st] = y1;
+                    if (m == 3) p[2 * st] = y2;
                 }
             } else
             for (int it0 = tid; it0 < nseg; it0 += SG * NSEGT) {
@@ -883,7 +923,7 @@ __device__ __forceinline__ void chase_la(SmemCore &S, double *A, int lda, int kt
                 const int m1 = min(3, kb - (k + 1));
                 const double r0 = (extra && tau != 0.0) ? -(tau * (v2 * ch)) : 0.0; // as the row segment computes it
                 double nv1, nv2, ntau, nbeta;
-                house3c(m1, x0, x1, (m1 == 3) ? r0 : 0.0, nv1, nv2, ntau, nbeta);
+                house3r(m1, x0, x1, (m1 == 3) ? r0 : 0.0, nv1, nv2, ntau, nbeta);
                 if (m1 < 3) nv2 = 0.0;
                 if (lane == 0) {
                     S.bv1[par ^ 1] = nv1;
