@@ -15,7 +15,7 @@ constexpr int WMAX = 96;           // largest bulge-chasing window
 constexpr int GMAX = 16;           // most bulges chased in one window
 constexpr int MAXWIN = 16;         // most windows in one chase round
 constexpr int MAXCAND = 1024;      // candidate eigenvalues returned by one AED step
-constexpr int MAX_UPDATE_K = 1024; // largest factor order k_update stages (16 x (1024 + 4) doubles of LDS)
+constexpr int MAX_UPDATE_K = 1024; // largest AED window (window copies and factor workspaces are sized for it)
 
 // Deflation conditions of the solver (Sec. 5.6, "Comment regarding the
 // deflation conditions and the accuracy").  thr < 0: LAPACK-style conditions
@@ -188,6 +188,11 @@ hipError_t restore_blocked(double *T, int64_t ldt, int nw, int ns, double *Vw, i
 
 // ---- launchers (hqr_gemm.hip) ----
 hipError_t launch_updates(const UpdBatch &b, hipStream_t s);
+void free_update_ws();
+// C = beta C + alpha op(A) op(B) (column major; op 1 = transposed), FP64 MFMA,
+// 64 x 64 tiles; tag 0 / 1 only selects the kernel name shown in profiles.
+hipError_t gemm_mfma(int tag, int mm, int nn, int kk, double alpha, const double *A, int64_t lda, int opA,
+                     const double *B, int64_t ldb, int opB, double beta, double *C, int64_t ldc, hipStream_t s);
 int update_tile(int K16, int side);
 
 } // namespace hqr

@@ -1005,7 +1005,7 @@ Params resolve(const hqr_params *pp, int n)
     P.aed_nw = p.aed_nw > 0 ? std::max(4, std::min(p.aed_nw, MMAX)) : 0;
     P.aed_nmin = p.aed_nmin > 0 ? std::max(12, std::min(p.aed_nmin, MMAX)) : 0;
     if (P.nw < 2) P.nw = 2;
-    P.nw = std::min(P.nw, MAX_UPDATE_K); // the window factor is applied by k_update
+    P.nw = std::min(P.nw, MAX_UPDATE_K);
     P.defl_mode = p.defl_mode;
     P.defl_thold = p.defl_thold;
     return P;
@@ -1194,6 +1194,7 @@ int hqr_profile_read(double *ms, int64_t *launches, double *flops, double *bytes
 
 int hqr_finalize(void)
 {
+    free_update_ws();
     for (auto &W : g_ws) {
         if (!W.init) continue;
         hipSetDevice(W.dev);

@@ -20,7 +20,7 @@
 //     kernel folds into Y (k_hh_col, one workgroup of 512 threads);
 //   * after the panel: A <- Q_p^T (A0 - Y V^T) on the columns right of the
 //     panel (extra columns R included in the left product) and Z <- Z Q_p,
-//     as FP64-MFMA matrix products (k_hh_gemm).
+//     as FP64-MFMA matrix products (k_gemm64).
 // Everything stays on the device: no host synchronization inside.
 #include "hqr_common.h"
 #include <algorithm>
@@ -225,83 +225,6 @@ __global__ void __launch_bounds__(256) k_hh_gemv(const double *A, int64_t lda, i
     part[(int64_t)q * m + r] = (s0 + s1) + (s2 + s3);
 }
 
-// C(0:mm, 0:nn) = beta C + alpha op(A) op(B), inner dimension kk, FP64 MFMA,
-// 64 x 64 tiles; opA/opB 0 = as stored (column major), 1 = transposed.
-constexpr int HGT = 64, HGK = 16, HGP = 4;
-__global__ void __launch_bounds__(256) k_hh_gemm(int mm, int nn, int kk, double alpha, const double *A, int64_t lda,
-                                                 int opA, const double *B, int64_t ldb, int opB, double beta,
-                                                 double *C, int64_t ldc)
-{
-    __shared__ double As[HGK][HGT + HGP];
-    __shared__ double Bs[HGK][HGT + HGP];
-    const int m0 = blockIdx.x * HGT, n0 = blockIdx.y * HGT;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-    const int l16 = lane & 15, lq = lane >> 4;
-    dbl4h acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = (dbl4h){0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < kk; k0 += HGK) {
-        for (int it = tid; it < HGT * HGK; it += 256) {
-            int mi, ki;
-            if (opA == 0) {
-                mi = it % HGT;
-                ki = it / HGT;
-            } else {
-                ki = it % HGK;
-                mi = it / HGK;
-            }
-            const int gm = m0 + mi, gk = k0 + ki;
-            double v = 0.0;
-            if (gm < mm && gk < kk) v = (opA == 0) ? A[gm + (int64_t)gk * lda] : A[gk + (int64_t)gm * lda];
-            As[ki][mi] = v;
-            int nj, kj;
-            if (opB == 0) {
-                kj = it % HGK;
-                nj = it / HGK;
-            } else {
-                nj = it % HGT;
-                kj = it / HGT;
-            }
-            const int gn = n0 + nj, gk2 = k0 + kj;
-            double w = 0.0;
-            if (gn < nn && gk2 < kk) w = (opB == 0) ? B[gk2 + (int64_t)gn * ldb] : B[gn + (int64_t)gk2 * ldb];
-            Bs[kj][nj] = w;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < HGK; ks += 4) {
-            double af[2], bf[2];
-            for (int a = 0; a < 2; ++a) af[a] = As[ks + lq][wm + a * 16 + l16];
-            for (int b = 0; b < 2; ++b) bf[b] = Bs[ks + lq][wn + b * 16 + l16];
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
-        }
-        __syncthreads();
-    }
-    // lane holds D[lq + 4r][l16] of each 16 x 16 block
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int r = 0; r < 4; ++r) {
-                const int gm = m0 + wm + a * 16 + lq + 4 * r;
-                const int gn = n0 + wn + b * 16 + l16;
-                if (gm < mm && gn < nn) {
-                    double *p = C + gm + (int64_t)gn * ldc;
-                    *p = (beta == 0.0 ? 0.0 : beta * *p) + alpha * acc[a][b][r];
-                }
-            }
-}
-
-static hipError_t hh_gemm(int mm, int nn, int kk, double alpha, const double *A, int64_t lda, int opA,
-                          const double *B, int64_t ldb, int opB, double beta, double *C, int64_t ldc, hipStream_t s)
-{
-    if (mm <= 0 || nn <= 0) return hipSuccess;
-    dim3 grid((mm + HGT - 1) / HGT, (nn + HGT - 1) / HGT);
-    hipLaunchKernelGGL(k_hh_gemm, grid, dim3(256), 0, s, mm, nn, kk, alpha, A, lda, opA, B, ldb, opB, beta, C, ldc);
-    return hipGetLastError();
-}
-
 // Spike reflector of a large AED window (Sec. 2.5): g = s * Z(0, 0:m) (row 0
 // of the window's factor), reflector P = I - tau u u^T with P g = beta e_1;
 // u, tau and beta go to hv (m + 2 doubles: u, tau, beta).  One workgroup.
@@ -406,26 +329,26 @@ hipError_t hess_reduce(double *A, int64_t lda, int m, int nr, double *Z, int64_t
         const int c1 = k + nb; // first column right of the panel
         const int r0 = k + 1;  // first row the reflectors touch
         // right: A(0:m, c1:m) -= Y V(c1:m, :)^T
-        if ((e = hh_gemm(m, m - c1, nb, -1.0, Y, m, 0, V + c1, m, 1, 1.0, A + (int64_t)c1 * lda, lda, s)) !=
+        if ((e = gemm_mfma(0, m, m - c1, nb, -1.0, Y, m, 0, V + c1, m, 1, 1.0, A + (int64_t)c1 * lda, lda, s)) !=
             hipSuccess)
             return e;
         // left: M = A(r0:m, c1:m+nr);  WL = V(r0:m, :)^T M;  M -= (V T^T)(r0:m, :) WL
         const int ncl = m + nr - c1;
-        if ((e = hh_gemm(nb, ncl, m - r0, 1.0, V + r0, m, 1, A + r0 + (int64_t)c1 * lda, lda, 0, 0.0, WL, NBH,
+        if ((e = gemm_mfma(0, nb, ncl, m - r0, 1.0, V + r0, m, 1, A + r0 + (int64_t)c1 * lda, lda, 0, 0.0, WL, NBH,
                          s)) != hipSuccess)
             return e;
-        if ((e = hh_gemm(m - r0, nb, nb, 1.0, V + r0, m, 0, Tm, NBH, 1, 0.0, VT + r0, m, s)) != hipSuccess)
+        if ((e = gemm_mfma(0, m - r0, nb, nb, 1.0, V + r0, m, 0, Tm, NBH, 1, 0.0, VT + r0, m, s)) != hipSuccess)
             return e;
-        if ((e = hh_gemm(m - r0, ncl, nb, -1.0, VT + r0, m, 0, WL, NBH, 0, 1.0, A + r0 + (int64_t)c1 * lda, lda,
+        if ((e = gemm_mfma(0, m - r0, ncl, nb, -1.0, VT + r0, m, 0, WL, NBH, 0, 1.0, A + r0 + (int64_t)c1 * lda, lda,
                          s)) != hipSuccess)
             return e;
         // Z(0:nz, r0:m) <- Z (I - V T V^T):  ZW = Z V;  ZT = ZW T;  Z -= ZT V^T
         if (Z && nz > 0) {
-            if ((e = hh_gemm(nz, nb, m - r0, 1.0, Z + (int64_t)r0 * ldz, ldz, 0, V + r0, m, 0, 0.0, ZW, nz, s)) !=
+            if ((e = gemm_mfma(0, nz, nb, m - r0, 1.0, Z + (int64_t)r0 * ldz, ldz, 0, V + r0, m, 0, 0.0, ZW, nz, s)) !=
                 hipSuccess)
                 return e;
-            if ((e = hh_gemm(nz, nb, nb, 1.0, ZW, nz, 0, Tm, NBH, 0, 0.0, ZT, nz, s)) != hipSuccess) return e;
-            if ((e = hh_gemm(nz, m - r0, nb, -1.0, ZT, nz, 0, V + r0, m, 1, 1.0, Z + (int64_t)r0 * ldz, ldz, s)) !=
+            if ((e = gemm_mfma(0, nz, nb, nb, 1.0, ZW, nz, 0, Tm, NBH, 0, 0.0, ZT, nz, s)) != hipSuccess) return e;
+            if ((e = gemm_mfma(0, nz, m - r0, nb, -1.0, ZT, nz, 0, V + r0, m, 1, 1.0, Z + (int64_t)r0 * ldz, ldz, s)) !=
                 hipSuccess)
                 return e;
         }

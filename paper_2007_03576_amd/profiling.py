@@ -5,7 +5,7 @@ import ctypes
 from ._lib import lib
 
 CLASSES = ["lds_iteration", "chase_windows", "update_gemm", "large_aed", "other"]
-KERNELS = {"lds_iteration": "k_iter", "chase_windows": "k_chase", "update_gemm": "k_update",
+KERNELS = {"lds_iteration": "k_iter", "chase_windows": "k_chase", "update_gemm": "k_update_s/k_gemm64",
            "large_aed": "k_corner_deflate/k_restore_global", "other": "k_fin_*/k_find_block"}
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0
