@@ -271,241 +271,6 @@ __device__ inline void refl3(int m, double tau, double v1, double v2, double &y0
     if (m == 3) y2 -= s * v2;
 }
 
-// Chase nb bulges through the matrix held in LDS (or global memory).  Indices
-// are global; local index = global - off.  Active block [ktop,kbot].  Bulge b
-// is at position p0 + t - 3b at step t and acts when ktop-1 <= k <= kend (a
-// reflector at k acts on rows/columns k+1..k+3).  Left application: local
-// columns up to colhi; right application: local rows 0..min(k+4,kbot); Z (nz
-// rows) accumulates.
-//
-// One step applies the reflectors of all active bulges in a single barrier
-// phase.  The regions they touch are split so that no element is written by
-// two threads: each bulge's own m x m block (P^T B P), the cross blocks between
-// the rows of a higher bulge and the columns of a lower one (P_hi^T X P_lo),
-// the left products right of the lowest active block, the right products
-// above the highest active block plus each bulge's row k+4, and Z.  For a
-// single bulge every thread computes the reflector itself (no barrier before
-// the products) and the bulge column is written one step later, when no
-// thread reads it any more.
-template <int NTH = NT>
-__device__ __forceinline__ void chain_chase(SmemCore &S, double *A, int lda, int off, int ktop, int kbot, int p0, int nsteps,
-                            int kend, int nb, int colhi, double *Z, int ldz, int nz)
-{
-    const int tid = threadIdx.x;
-    const int kbl = kbot - off;
-    // pending bulge-column write for the single-bulge path (thread 0)
-    int pend_kl = -1, pend_m = 0;
-    double pend_beta = 0.0;
-    double fl = 0.0;
-    for (int t = 0; t < nsteps; ++t) {
-        int blo = nb, bhi = -1;
-        double r_v1 = 0.0, r_v2 = 0.0, r_tau = 0.0, r_beta = 0.0;
-        int r_m = 0, r_kl = 0;
-        if (nb == 1) {
-            int k = p0 + t;
-            if (k >= ktop - 1 && k <= kend) {
-                bulge_reflector(S, A, lda, off, ktop, kbot, 0, k, r_m, r_v1, r_v2, r_tau, r_beta);
-                r_kl = k - off;
-                blo = bhi = 0;
-                // the introduction reads the leading block, which the products overwrite
-                if (k == ktop - 1) __syncthreads();
-            }
-        } else {
-            if (tid < nb) {
-                int b = tid;
-                int k = p0 + t - 3 * b;
-                int m = 0;
-                if (k >= ktop - 1 && k <= kend) {
-                    double v1, v2, tau, beta;
-                    bulge_reflector(S, A, lda, off, ktop, kbot, b, k, m, v1, v2, tau, beta);
-                    const int kl = k - off;
-                    if (k >= ktop) {
-                        A[(kl + 1) + kl * lda] = beta;
-                        A[(kl + 2) + kl * lda] = 0.0;
-                        if (m == 3) A[(kl + 3) + kl * lda] = 0.0;
-                    }
-                    S.bk[b] = kl;
-                    S.bv1[b] = v1;
-                    S.bv2[b] = v2;
-                    S.btau[b] = tau;
-                }
-                S.bm[b] = m;
-            }
-            __syncthreads();
-            for (int b = 0; b < nb; ++b)
-                if (S.bm[b] != 0) {
-                    blo = min(blo, b);
-                    bhi = max(bhi, b);
-                }
-        }
-        if (bhi < 0) {
-            if (nb > 1) __syncthreads();
-            continue;
-        }
-        if (tid == 0) {
-            S.nphase += 1;
-            S.nbstep += bhi - blo + 1;
-        }
-        // geometry of this step (uniform across threads)
-        auto KL = [&](int b) { return nb == 1 ? r_kl : S.bk[b]; };
-        auto M = [&](int b) { return nb == 1 ? r_m : S.bm[b]; };
-        auto TAU = [&](int b) { return nb == 1 ? r_tau : S.btau[b]; };
-        auto V1 = [&](int b) { return nb == 1 ? r_v1 : S.bv1[b]; };
-        auto V2 = [&](int b) { return nb == 1 ? r_v2 : S.bv2[b]; };
-        const int nact = bhi - blo + 1;
-        const int klo = KL(blo), mlo = M(blo);
-        const int khi = KL(bhi);
-        const int c0L = klo + mlo + 1;             // free left columns: c0L..colhi
-        const int ncL = max(0, colhi - c0L + 1);
-        const int nrR = max(0, khi + 1);           // free right rows: 0..khi
-        const int perR = nrR + nz + 1;             // + Z rows + row k+4
-        const int npairs = nact * (nact - 1) / 2;
-        const int nL = nact * ncL, nR = nact * perR;
-        const int total = nL + nR + nact + npairs;
-        if (tid == 0) fl += 4.0 * 3.0 * (double)(nL + nR) + 40.0 * (nact + npairs);
-        for (int it = tid; it < total; it += NTH) {
-            if (it < nL) {
-                const int b = blo + it / ncL, c = c0L + it % ncL;
-                const int m = M(b), r = KL(b) + 1;
-                const double tau = TAU(b);
-                if (tau == 0.0) continue;
-                double *col = A + c * lda + r;
-                double y0 = col[0], y1 = col[1], y2 = (m == 3) ? col[2] : 0.0;
-                refl3(m, tau, V1(b), V2(b), y0, y1, y2);
-                col[0] = y0;
-                col[1] = y1;
-                if (m == 3) col[2] = y2;
-            } else if (it < nL + nR) {
-                const int q = it - nL;
-                const int b = blo + q / perR, r = q % perR;
-                const int m = M(b), kl = KL(b);
-                const double tau = TAU(b);
-                if (tau == 0.0) continue;
-                double *Mx;
-                int ld;
-                if (r < nrR) {
-                    Mx = A + r;
-                    ld = lda;
-                } else if (r < nrR + nz) {
-                    Mx = Z + (r - nrR);
-                    ld = ldz;
-                } else {
-                    if (m != 3 || kl + 4 > kbl) continue;
-                    Mx = A + (kl + 4);
-                    ld = lda;
-                }
-                double y0 = Mx[(kl + 1) * ld], y1 = Mx[(kl + 2) * ld], y2 = (m == 3) ? Mx[(kl + 3) * ld] : 0.0;
-                refl3(m, tau, V1(b), V2(b), y0, y1, y2);
-                Mx[(kl + 1) * ld] = y0;
-                Mx[(kl + 2) * ld] = y1;
-                if (m == 3) Mx[(kl + 3) * ld] = y2;
-            } else if (it < nL + nR + nact) {
-                // own block: B <- P^T B P on rows/columns kl+1..kl+m (m = 2 is the 3x3
-                // case with v2 = 0 and the third row/column left out)
-                const int b = blo + (it - nL - nR);
-                const int m = M(b), kl = KL(b);
-                const double tau = TAU(b), v1 = V1(b), v2 = V2(b);
-                if (tau == 0.0) continue;
-                double B00, B01, B02, B10, B11, B12, B20 = 0.0, B21 = 0.0, B22 = 0.0;
-                double *a = A + (kl + 1) + (kl + 1) * lda;
-                B00 = a[0];
-                B10 = a[1];
-                B01 = a[lda];
-                B11 = a[1 + lda];
-                B02 = (m == 3) ? a[2 * lda] : 0.0;
-                B12 = (m == 3) ? a[1 + 2 * lda] : 0.0;
-                if (m == 3) {
-                    B20 = a[2];
-                    B21 = a[2 + lda];
-                    B22 = a[2 + 2 * lda];
-                }
-                refl3(3, tau, v1, v2, B00, B10, B20);
-                refl3(3, tau, v1, v2, B01, B11, B21);
-                refl3(3, tau, v1, v2, B02, B12, B22);
-                refl3(3, tau, v1, v2, B00, B01, B02);
-                refl3(3, tau, v1, v2, B10, B11, B12);
-                refl3(3, tau, v1, v2, B20, B21, B22);
-                a[0] = B00;
-                a[1] = B10;
-                a[lda] = B01;
-                a[1 + lda] = B11;
-                if (m == 3) {
-                    a[2] = B20;
-                    a[2 + lda] = B21;
-                    a[2 * lda] = B02;
-                    a[1 + 2 * lda] = B12;
-                    a[2 + 2 * lda] = B22;
-                }
-            } else if (it < nL + nR + nact + npairs) {
-                // cross block: rows of bulge bu (higher) x columns of bulge bd (lower)
-                int p = it - nL - nR - nact;
-                int i = 0;
-                while (p >= nact - 1 - i) {
-                    p -= nact - 1 - i;
-                    ++i;
-                }
-                const int bd = blo + i, bu = blo + i + 1 + p;
-                const int mu = M(bu), md = M(bd), ku = KL(bu), kd = KL(bd);
-                const double tu = TAU(bu), td = TAU(bd);
-                const double u1 = V1(bu), u2 = V2(bu), d1 = V1(bd), d2 = V2(bd);
-                double *x = A + (ku + 1) + (kd + 1) * lda;
-                double X00 = x[0], X10 = x[1], X20 = (mu == 3) ? x[2] : 0.0;
-                double X01 = x[lda], X11 = x[1 + lda], X21 = (mu == 3) ? x[2 + lda] : 0.0;
-                double X02 = 0.0, X12 = 0.0, X22 = 0.0;
-                if (md == 3) {
-                    X02 = x[2 * lda];
-                    X12 = x[1 + 2 * lda];
-                    X22 = (mu == 3) ? x[2 + 2 * lda] : 0.0;
-                }
-                if (tu != 0.0) {
-                    refl3(3, tu, u1, u2, X00, X10, X20);
-                    refl3(3, tu, u1, u2, X01, X11, X21);
-                    refl3(3, tu, u1, u2, X02, X12, X22);
-                }
-                if (td != 0.0) {
-                    refl3(3, td, d1, d2, X00, X01, X02);
-                    refl3(3, td, d1, d2, X10, X11, X12);
-                    refl3(3, td, d1, d2, X20, X21, X22);
-                }
-                x[0] = X00;
-                x[1] = X10;
-                x[lda] = X01;
-                x[1 + lda] = X11;
-                if (mu == 3) {
-                    x[2] = X20;
-                    x[2 + lda] = X21;
-                }
-                if (md == 3) {
-                    x[2 * lda] = X02;
-                    x[1 + 2 * lda] = X12;
-                    if (mu == 3) x[2 + 2 * lda] = X22;
-                }
-            }
-        }
-        if (nb == 1 && tid == 0) {
-            // single bulge: write the previous step's bulge column (nobody reads it now)
-            if (pend_m > 0) {
-                A[(pend_kl + 1) + pend_kl * lda] = pend_beta;
-                A[(pend_kl + 2) + pend_kl * lda] = 0.0;
-                if (pend_m == 3) A[(pend_kl + 3) + pend_kl * lda] = 0.0;
-            }
-            pend_m = (r_kl + off >= ktop) ? r_m : 0;
-            pend_kl = r_kl;
-            pend_beta = r_beta;
-        }
-        __syncthreads();
-    }
-    if (nb == 1) {
-        if (tid == 0 && pend_m > 0) {
-            A[(pend_kl + 1) + pend_kl * lda] = pend_beta;
-            A[(pend_kl + 2) + pend_kl * lda] = 0.0;
-            if (pend_m == 3) A[(pend_kl + 3) + pend_kl * lda] = 0.0;
-        }
-        __syncthreads();
-    }
-    if (tid == 0) S.flops += fl;
-}
-
 // 1/d from the hardware reciprocal (about 28 correct bits) and two Newton
 // steps (within an ulp; measured 0.5 ulp over binades 2^-100..2^100).
 __device__ inline double rcp_nr(double d)
@@ -582,6 +347,311 @@ __device__ inline void house3r(int m, double x0, double x1, double x2, double &v
     } else {
         house3(m, x0, x1, x2, v1, v2, tau, beta);
     }
+}
+
+// Chase nb bulges through the matrix held in LDS (or global memory).  Indices
+// are global; local index = global - off.  Active block [ktop,kbot].  Bulge b
+// is at position p0 + t - 3b at step t and acts when ktop-1 <= k <= kend (a
+// reflector at k acts on rows/columns k+1..k+3).  Left application: local
+// columns up to colhi; right application: local rows 0..min(k+4,kbot); Z (nz
+// rows) accumulates.
+//
+// One step applies the reflectors of all active bulges in a single barrier
+// phase.  The regions they touch are split so that no element is written by
+// two threads: each bulge's own m x m block (P^T B P), the cross blocks between
+// the rows of a higher bulge and the columns of a lower one (P_hi^T X P_lo),
+// the left products right of the lowest active block, the right products
+// above the highest active block plus each bulge's row k+4, and Z.  The
+// geometry of a step (active bulges, positions, orders) follows from t alone
+// and is computed by every thread; only the reflectors pass through LDS, one
+// thread per bulge forming them before the products.  For a single bulge
+// every thread computes the reflector itself (no barrier before the products)
+// and the bulge column is written one step later, when no thread reads it
+// any more.
+template <int NTH = NT>
+__device__ __forceinline__ void chain_chase(SmemCore &S, double *A, int lda, int off, int ktop, int kbot, int p0, int nsteps,
+                            int kend, int nb, int colhi, double *Z, int ldz, int nz)
+{
+    const int tid = threadIdx.x;
+    const int kbl = kbot - off;
+    double fl = 0.0;
+    if (nb == 1) {
+        // pending bulge-column write (thread 0)
+        int pend_kl = -1, pend_m = 0;
+        double pend_beta = 0.0;
+        for (int t = 0; t < nsteps; ++t) {
+            const int k = p0 + t;
+            if (k < ktop - 1 || k > kend) continue;
+            int m;
+            double v1, v2, tau, beta;
+            bulge_reflector(S, A, lda, off, ktop, kbot, 0, k, m, v1, v2, tau, beta);
+            const int kl = k - off;
+            // the introduction reads the leading block, which the products overwrite
+            if (k == ktop - 1) __syncthreads();
+            if (tid == 0) {
+                S.nphase += 1;
+                S.nbstep += 1;
+            }
+            const int c0L = kl + m + 1;
+            const int ncL = max(0, colhi - c0L + 1);
+            const int nrR = max(0, kl + 1);
+            const int perR = nrR + nz + 1;
+            const int total = ncL + perR + 1;
+            if (tid == 0) fl += 4.0 * 3.0 * (double)(ncL + perR) + 40.0;
+            if (tau != 0.0)
+                for (int it = tid; it < total; it += NTH) {
+                    if (it < ncL) {
+                        double *col = A + (c0L + it) * lda + kl + 1;
+                        double y0 = col[0], y1 = col[1], y2 = (m == 3) ? col[2] : 0.0;
+                        refl3(m, tau, v1, v2, y0, y1, y2);
+                        col[0] = y0;
+                        col[1] = y1;
+                        if (m == 3) col[2] = y2;
+                    } else if (it < ncL + perR) {
+                        const int r = it - ncL;
+                        double *Mx;
+                        int ld;
+                        if (r < nrR) {
+                            Mx = A + r;
+                            ld = lda;
+                        } else if (r < nrR + nz) {
+                            Mx = Z + (r - nrR);
+                            ld = ldz;
+                        } else {
+                            if (m != 3 || kl + 4 > kbl) continue;
+                            Mx = A + (kl + 4);
+                            ld = lda;
+                        }
+                        double y0 = Mx[(kl + 1) * ld], y1 = Mx[(kl + 2) * ld], y2 = (m == 3) ? Mx[(kl + 3) * ld] : 0.0;
+                        refl3(m, tau, v1, v2, y0, y1, y2);
+                        Mx[(kl + 1) * ld] = y0;
+                        Mx[(kl + 2) * ld] = y1;
+                        if (m == 3) Mx[(kl + 3) * ld] = y2;
+                    } else {
+                        double *a = A + (kl + 1) + (kl + 1) * lda;
+                        double B00 = a[0], B10 = a[1], B01 = a[lda], B11 = a[1 + lda];
+                        double B02 = (m == 3) ? a[2 * lda] : 0.0, B12 = (m == 3) ? a[1 + 2 * lda] : 0.0;
+                        double B20 = (m == 3) ? a[2] : 0.0, B21 = (m == 3) ? a[2 + lda] : 0.0;
+                        double B22 = (m == 3) ? a[2 + 2 * lda] : 0.0;
+                        refl3(3, tau, v1, v2, B00, B10, B20);
+                        refl3(3, tau, v1, v2, B01, B11, B21);
+                        refl3(3, tau, v1, v2, B02, B12, B22);
+                        refl3(3, tau, v1, v2, B00, B01, B02);
+                        refl3(3, tau, v1, v2, B10, B11, B12);
+                        refl3(3, tau, v1, v2, B20, B21, B22);
+                        a[0] = B00;
+                        a[1] = B10;
+                        a[lda] = B01;
+                        a[1 + lda] = B11;
+                        if (m == 3) {
+                            a[2] = B20;
+                            a[2 + lda] = B21;
+                            a[2 * lda] = B02;
+                            a[1 + 2 * lda] = B12;
+                            a[2 + 2 * lda] = B22;
+                        }
+                    }
+                }
+            if (tid == 0) {
+                // write the previous step's bulge column (nobody reads it now)
+                if (pend_m > 0) {
+                    A[(pend_kl + 1) + pend_kl * lda] = pend_beta;
+                    A[(pend_kl + 2) + pend_kl * lda] = 0.0;
+                    if (pend_m == 3) A[(pend_kl + 3) + pend_kl * lda] = 0.0;
+                }
+                pend_m = (k >= ktop) ? m : 0;
+                pend_kl = kl;
+                pend_beta = beta;
+            }
+            __syncthreads();
+        }
+        if (tid == 0 && pend_m > 0) {
+            A[(pend_kl + 1) + pend_kl * lda] = pend_beta;
+            A[(pend_kl + 2) + pend_kl * lda] = 0.0;
+            if (pend_m == 3) A[(pend_kl + 3) + pend_kl * lda] = 0.0;
+        }
+        if (tid == 0) S.flops += fl;
+        __syncthreads();
+        return;
+    }
+    for (int t = 0; t < nsteps; ++t) {
+        // active bulges b: ktop - 1 <= p0 + t - 3b <= kend
+        const int k0 = p0 + t;
+        const int blo = max(0, (k0 - kend + 2 + 3 * NTH) / 3 - NTH);            // ceil((k0 - kend) / 3)
+        const int bhi = min(nb - 1, (k0 - (ktop - 1) + 3 * NTH) / 3 - NTH);     // floor((k0 - ktop + 1) / 3)
+        if (blo > bhi) continue;
+        if (tid >= blo && tid <= bhi) {
+            const int b = tid, k = k0 - 3 * b;
+            const int m = min(3, kbot - k);
+            const int kl = k - off;
+            double x0, x1, x2;
+            if (k == ktop - 1) {
+                shift_column(A, lda, kl + 1, kbl, S.sr[2 * b], S.si[2 * b], S.sr[2 * b + 1], S.si[2 * b + 1], x0, x1,
+                             x2);
+            } else {
+                x0 = A[(kl + 1) + kl * lda];
+                x1 = A[(kl + 2) + kl * lda];
+                x2 = (m == 3) ? A[(kl + 3) + kl * lda] : 0.0;
+            }
+            double v1, v2, tau, beta;
+            house3r(m, x0, x1, x2, v1, v2, tau, beta);
+            if (m < 3) v2 = 0.0;
+            if (k >= ktop) {
+                A[(kl + 1) + kl * lda] = beta;
+                A[(kl + 2) + kl * lda] = 0.0;
+                if (m == 3) A[(kl + 3) + kl * lda] = 0.0;
+            }
+            S.bv1[b] = v1;
+            S.bv2[b] = v2;
+            S.btau[b] = tau;
+        }
+        __syncthreads();
+        const int nact = bhi - blo + 1;
+        if (tid == 0) {
+            S.nphase += 1;
+            S.nbstep += nact;
+        }
+        // bulge b: local position k0 - 3b - off, order min(3, kbot - (k0 - 3b))
+        auto KL = [&](int b) { return k0 - 3 * b - off; };
+        auto M = [&](int b) { return min(3, kbot - (k0 - 3 * b)); };
+        const int klo = KL(blo), mlo = M(blo);
+        const int khi = KL(bhi);
+        const int c0L = klo + mlo + 1;             // free left columns: c0L..colhi
+        const int ncL = max(0, colhi - c0L + 1);
+        const int nrR = max(0, khi + 1);           // free right rows: 0..khi
+        const int perR = nrR + nz + 1;             // + Z rows + row k+4
+        const int npairs = nact * (nact - 1) / 2;
+        const int nL = nact * ncL, nR = nact * perR;
+        const int total = nL + nR + nact + npairs;
+        // it / ncL and q / perR through single-precision reciprocals: exact,
+        // since the quotients are at least 1/(2 n) from an integer and the
+        // counts are far below 2^20
+        const float rL = 1.0f / (float)max(ncL, 1), rR = 1.0f / (float)perR;
+        if (tid == 0) fl += 4.0 * 3.0 * (double)(nL + nR) + 40.0 * (nact + npairs);
+        for (int it = tid; it < total; it += NTH) {
+            if (it < nL) {
+                const int bi = (int)(((float)it + 0.5f) * rL);
+                const int b = blo + bi, c = c0L + (it - bi * ncL);
+                const double tau = S.btau[b], v1 = S.bv1[b], v2 = S.bv2[b];
+                const int m = M(b), r = KL(b) + 1;
+                double *col = A + c * lda + r;
+                double y0 = col[0], y1 = col[1], y2 = (m == 3) ? col[2] : 0.0;
+                if (tau == 0.0) continue;
+                refl3(m, tau, v1, v2, y0, y1, y2);
+                col[0] = y0;
+                col[1] = y1;
+                if (m == 3) col[2] = y2;
+            } else if (it < nL + nR) {
+                const int q = it - nL;
+                const int bi = (int)(((float)q + 0.5f) * rR);
+                const int b = blo + bi, r = q - bi * perR;
+                const int m = M(b), kl = KL(b);
+                double *Mx;
+                int ld;
+                if (r < nrR) {
+                    Mx = A + r;
+                    ld = lda;
+                } else if (r < nrR + nz) {
+                    Mx = Z + (r - nrR);
+                    ld = ldz;
+                } else {
+                    if (m != 3 || kl + 4 > kbl) continue;
+                    Mx = A + (kl + 4);
+                    ld = lda;
+                }
+                const double tau = S.btau[b], v1 = S.bv1[b], v2 = S.bv2[b];
+                double y0 = Mx[(kl + 1) * ld], y1 = Mx[(kl + 2) * ld], y2 = (m == 3) ? Mx[(kl + 3) * ld] : 0.0;
+                if (tau == 0.0) continue;
+                refl3(m, tau, v1, v2, y0, y1, y2);
+                Mx[(kl + 1) * ld] = y0;
+                Mx[(kl + 2) * ld] = y1;
+                if (m == 3) Mx[(kl + 3) * ld] = y2;
+            } else if (it < nL + nR + nact) {
+                // own block: B <- P^T B P on rows/columns kl+1..kl+m (m = 2 is the 3x3
+                // case with v2 = 0 and the third row/column left out)
+                const int b = blo + (it - nL - nR);
+                const int m = M(b), kl = KL(b);
+                const double tau = S.btau[b], v1 = S.bv1[b], v2 = S.bv2[b];
+                if (tau == 0.0) continue;
+                double B00, B01, B02, B10, B11, B12, B20 = 0.0, B21 = 0.0, B22 = 0.0;
+                double *a = A + (kl + 1) + (kl + 1) * lda;
+                B00 = a[0];
+                B10 = a[1];
+                B01 = a[lda];
+                B11 = a[1 + lda];
+                B02 = (m == 3) ? a[2 * lda] : 0.0;
+                B12 = (m == 3) ? a[1 + 2 * lda] : 0.0;
+                if (m == 3) {
+                    B20 = a[2];
+                    B21 = a[2 + lda];
+                    B22 = a[2 + 2 * lda];
+                }
+                refl3(3, tau, v1, v2, B00, B10, B20);
+                refl3(3, tau, v1, v2, B01, B11, B21);
+                refl3(3, tau, v1, v2, B02, B12, B22);
+                refl3(3, tau, v1, v2, B00, B01, B02);
+                refl3(3, tau, v1, v2, B10, B11, B12);
+                refl3(3, tau, v1, v2, B20, B21, B22);
+                a[0] = B00;
+                a[1] = B10;
+                a[lda] = B01;
+                a[1 + lda] = B11;
+                if (m == 3) {
+                    a[2] = B20;
+                    a[2 + lda] = B21;
+                    a[2 * lda] = B02;
+                    a[1 + 2 * lda] = B12;
+                    a[2 + 2 * lda] = B22;
+                }
+            } else {
+                // cross block: rows of bulge bu (higher) x columns of bulge bd (lower)
+                int pp = it - nL - nR - nact;
+                int i = 0;
+                while (pp >= nact - 1 - i) {
+                    pp -= nact - 1 - i;
+                    ++i;
+                }
+                const int bd = blo + i, bu = blo + i + 1 + pp;
+                const int mu = M(bu), md = M(bd), ku = KL(bu), kd = KL(bd);
+                const double tu = S.btau[bu], td = S.btau[bd];
+                const double u1 = S.bv1[bu], u2 = S.bv2[bu], d1 = S.bv1[bd], d2 = S.bv2[bd];
+                double *x = A + (ku + 1) + (kd + 1) * lda;
+                double X00 = x[0], X10 = x[1], X20 = (mu == 3) ? x[2] : 0.0;
+                double X01 = x[lda], X11 = x[1 + lda], X21 = (mu == 3) ? x[2 + lda] : 0.0;
+                double X02 = 0.0, X12 = 0.0, X22 = 0.0;
+                if (md == 3) {
+                    X02 = x[2 * lda];
+                    X12 = x[1 + 2 * lda];
+                    X22 = (mu == 3) ? x[2 + 2 * lda] : 0.0;
+                }
+                if (tu != 0.0) {
+                    refl3(3, tu, u1, u2, X00, X10, X20);
+                    refl3(3, tu, u1, u2, X01, X11, X21);
+                    refl3(3, tu, u1, u2, X02, X12, X22);
+                }
+                if (td != 0.0) {
+                    refl3(3, td, d1, d2, X00, X01, X02);
+                    refl3(3, td, d1, d2, X10, X11, X12);
+                    refl3(3, td, d1, d2, X20, X21, X22);
+                }
+                x[0] = X00;
+                x[1] = X10;
+                x[lda] = X01;
+                x[1 + lda] = X11;
+                if (mu == 3) {
+                    x[2] = X20;
+                    x[2 + lda] = X21;
+                }
+                if (md == 3) {
+                    x[2 * lda] = X02;
+                    x[1 + 2 * lda] = X12;
+                    if (mu == 3) x[2 + 2 * lda] = X22;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) S.flops += fl;
 }
 
 // Single-bulge chase (one double-shift sweep) through the matrix held in LDS:
