@@ -32,20 +32,34 @@ typedef double dbl4h __attribute__((ext_vector_type(4)));
 
 constexpr int HT = 512; // threads of the panel-column kernel (register budget 256)
 
-// Sum of `cnt` per-thread partial values (cnt <= NBH) over the workgroup;
-// every thread receives all sums in out[] (LDS scratch red: 16 x NBH).
+// Sum of `cnt` per-thread partial values (cnt <= NBH = 32) over the
+// workgroup; every thread receives all sums in out[] (LDS scratch red:
+// 16 x NBH).  Within a wave the 32 values are reduced by halving exchanges:
+// at the stage with partner lane ^ d (d = 32, 16, .., 2) each lane keeps the
+// half of its values selected by its bit d and adds the partner's copy of
+// that half, so 31 exchanges leave lanes 2i and 2i + 1 with the partial sums
+// of value i over their 32-lane halves, and one more exchange completes them.
 __device__ inline void hh_multi_sum(const double (&vals)[NBH], int cnt, double *red, double *out)
 {
+    static_assert(NBH == 32, "halving exchange assumes 32 values");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    __syncthreads(); // earlier readers of red are done
+    double v[NBH];
 #pragma unroll
-    for (int i = 0; i < NBH; ++i) {
-        if (i < cnt) {
-            double v = vals[i];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0) red[wave * NBH + i] = v;
+    for (int i = 0; i < NBH; ++i) v[i] = vals[i];
+#pragma unroll
+    for (int w = NBH, d = 32; w > 1; w >>= 1, d >>= 1) {
+        const bool up = (lane & d) != 0;
+        const int h = w >> 1;
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            const double send = up ? v[i] : v[i + h];
+            const double keep = up ? v[i + h] : v[i];
+            v[i] = keep + __shfl_xor(send, d, 64);
         }
     }
+    const double tot = v[0] + __shfl_xor(v[0], 1, 64);
+    __syncthreads(); // earlier readers of red are done
+    if ((lane & 1) == 0) red[wave * NBH + (lane >> 1)] = tot;
     __syncthreads();
     if ((int)threadIdx.x < cnt) {
         double t = 0.0;
@@ -77,6 +91,29 @@ __device__ inline double hh_max(double v, double *red)
     double t = 0.0;
     for (int w = 0; w < nw; ++w) t = fmax(t, red[w]);
     return t;
+}
+
+// Workgroup max of a and sum of b in one exchange (both returned in place).
+__device__ inline void hh_max_sum(double &a, double &b, double *red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) {
+        a = fmax(a, __shfl_xor(a, off, 64));
+        b += __shfl_xor(b, off, 64);
+    }
+    __syncthreads();
+    if (lane == 0) {
+        red[2 * wave] = a;
+        red[2 * wave + 1] = b;
+    }
+    __syncthreads();
+    double ta = 0.0, tb = 0.0;
+    for (int w = 0; w < nw; ++w) {
+        ta = fmax(ta, red[2 * w]);
+        tb += red[2 * w + 1];
+    }
+    a = ta;
+    b = tb;
 }
 
 // Panel step j (column c = k + j) of a matrix of order m, leading dimension
@@ -145,7 +182,7 @@ __global__ void __launch_bounds__(HT) k_hh_col(double *A, int64_t lda, int m, in
         sv2[tid] = t;
     }
     __syncthreads();
-    double amax = 0.0;
+    double amax = 0.0, ssr = 0.0;
     for (int r = tid; r < m; r += HT) {
         double v = x[r];
         if (r >= k + 1) {
@@ -155,20 +192,30 @@ __global__ void __launch_bounds__(HT) k_hh_col(double *A, int64_t lda, int m, in
         }
         x[r] = v;
         if (r <= c) A[r + (int64_t)c * lda] = v; // final rows 0..c of column c
-        if (r >= c + 2) amax = fmax(amax, fabs(v));
+        if (r >= c + 2) {
+            amax = fmax(amax, fabs(v));
+            ssr = fma(v, v, ssr);
+        }
     }
-    amax = hh_max(amax, red);
+    // the tail's largest entry and unscaled sum of squares in one reduction;
+    // the scaled pass runs only when the squares could over- or underflow
+    hh_max_sum(amax, ssr, red);
     const double x0 = x[c + 1]; // read before any thread overwrites x below
-    double ss = 0.0;
-    if (amax > 0.0)
+    double tnorm = 0.0;
+    if (amax >= 0x1p-480 && amax <= 0x1p+480) {
+        tnorm = sqrt(ssr);
+    } else if (amax > 0.0) {
+        double ss = 0.0;
         for (int r = c + 2 + tid; r < m; r += HT) {
             const double t = x[r] / amax;
             ss += t * t;
         }
-    ss = hh_sum(ss, red);
+        ss = hh_sum(ss, red);
+        tnorm = amax * sqrt(ss);
+    }
     double tj = 0.0, beta = x0, scal = 0.0;
     if (amax > 0.0) {
-        const double nrm = hypot(x0, amax * sqrt(ss));
+        const double nrm = hypot(x0, tnorm);
         beta = (x0 >= 0.0) ? -nrm : nrm;
         tj = (beta - x0) / beta;
         scal = 1.0 / (x0 - beta);
