@@ -141,10 +141,20 @@ def grad_run(seed):
     import paper_2007_03576_amd as hq
     from paper_2007_03576_amd import autotune
     H, _ = hi.prescribed_batch_device(512, 512, seed=seed, device="cuda")
-    # AED window / shifts and launch shape for 512 matrices of order 512
-    table = autotune.tune_table(buckets=((512, 512),), count=512, seed=seed + 9)
-    shape = autotune.tune(512, 512, count=512, seed=seed + 3,
+    # AED window / shifts and launch shape for 512 matrices of order 512, tuned
+    # on 256 other matrices of the same kind (prescribed spectra converge far more
+    # slowly than Gaussian Hessenberg matrices, so a Gaussian sample would
+    # pick other settings)
+    Ht, _ = hi.prescribed_batch_device(256, 512, seed=seed + 9, device="cuda")
+    packed_t = Ht.transpose(1, 2).contiguous().reshape(-1)
+
+    def same_kind(lo, hi_, count, sd, dev):
+        return [512] * Ht.shape[0], packed_t
+
+    table = autotune.tune_table(buckets=((512, 512),), seed=seed + 9, sampler=same_kind)
+    shape = autotune.tune(512, 512, seed=seed + 3, sampler=same_kind,
                           candidates=((1, 4095), (2, 4095), (2, 320), (3, 320), (4, 320)))
+    del Ht, packed_t
     fw = bw = None
     X = None
     for _ in range(2):

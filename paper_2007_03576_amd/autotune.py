@@ -15,7 +15,7 @@ batched form.
 from __future__ import annotations
 
 import time
-from typing import Dict, Sequence, Tuple
+from typing import Callable, Dict, Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -37,15 +37,21 @@ def sample(lo: int, hi: int, count: int, seed: int, device) -> tuple:
     return [int(s) for s in sizes], api.pack(mats)
 
 
+Sampler = Callable[[int, int, int, int, torch.device], tuple]
+
+
 def tune(lo: int, hi: int, count: int = 0, seed: int = 7, device="cuda",
-         candidates: Sequence[Tuple[int, int]] = CANDIDATES, reps: int = 1, apply: bool = True) -> Dict:
+         candidates: Sequence[Tuple[int, int]] = CANDIDATES, reps: int = 1, apply: bool = True,
+         sampler: Optional[Sampler] = None) -> Dict:
     """Times hqr_schur_batched on `count` sampled matrices (default: four per
     CU) for each (wg_per_cu, wide_n) candidate; returns {"wg_per_cu",
-    "wide_n", "seconds": {candidate: s}} and installs the best if apply."""
+    "wide_n", "seconds": {candidate: s}} and installs the best if apply.
+    `sampler(lo, hi, count, seed, device) -> (sizes, packed)` replaces the
+    Gaussian sample when the workload's matrices are of another kind."""
     dev = torch.device(device)
     if count <= 0:
         count = 4 * torch.cuda.get_device_properties(dev).multi_processor_count
-    sizes, packed = sample(lo, hi, count, seed, dev)
+    sizes, packed = (sampler or sample)(lo, hi, count, seed, dev)
     prob = api.BatchedProblem(sizes, True, dev)
     prev = api.batched_launch()
     times = {}
@@ -79,12 +85,13 @@ BUCKETS: Tuple[Tuple[int, int], ...] = ((97, 128), (129, 192), (193, 256))
 
 def tune_table(buckets: Sequence[Tuple[int, int]] = BUCKETS, count: int = 0, seed: int = 11, device="cuda",
                candidates: Sequence[Tuple[int, int]] = TABLE_CANDIDATES, reps: int = 1,
-               apply: bool = True) -> Dict:
+               apply: bool = True, sampler: Optional[Sampler] = None) -> Dict:
     """Times hqr_schur_batched on a seeded sample of each size bucket (orders
     uniform in the bucket, `count` matrices, default two per CU) for every
     (nw, ns) candidate and keeps the fastest whose solves all succeeded; the
     last bucket also takes every larger order.  Returns {"upper", "nw", "ns",
-    "seconds": {bucket: {candidate: s}}} and installs the table if apply."""
+    "seconds": {bucket: {candidate: s}}} and installs the table if apply.
+    `sampler` as for tune()."""
     dev = torch.device(device)
     if count <= 0:
         count = 2 * torch.cuda.get_device_properties(dev).multi_processor_count
@@ -92,7 +99,7 @@ def tune_table(buckets: Sequence[Tuple[int, int]] = BUCKETS, count: int = 0, see
     chosen_nw, chosen_ns, upper, secs = [], [], [], {}
     try:
         for bi, (lo, hi) in enumerate(buckets):
-            sizes, packed = sample(lo, hi, count, seed + bi, dev)
+            sizes, packed = (sampler or sample)(lo, hi, count, seed + bi, dev)
             prob = api.BatchedProblem(sizes, True, dev)
             times = {}
             for nw, ns in candidates:
