@@ -56,7 +56,19 @@ extern "C" {
  *              eigenvalues of the trailing block, Sec. 2.3)
  *   aed_ns, aed_nw, aed_nmin  ns, nw and nmin of the recursive solve that
  *              reduces an AED window larger than the one-workgroup solver
- *              (the AED reduce state of Sec. 3.3); nw is capped at 96 */
+ *              (the AED reduce state of Sec. 3.3); nw is capped at 96
+ *   aed_mode   how AED windows larger than 96 run (Sec. 3.5, "Adaptive
+ *              approach"): 0 = adaptive, 1 = sequential whenever the window
+ *              is at most aed_seq_max, 2 = always parallel.  Sequential: one
+ *              workgroup reduces the window, tests every candidate and
+ *              reorders the failures.  Parallel: the recursive solve on many
+ *              kernels, then chains of deflation and reordering windows.
+ *              Adaptive: sequential when the predicted time of the sequential
+ *              AED (a w^3, a refined from the measured sequential AEDs) is
+ *              below the predicted time of the update work still queued on
+ *              the deferred stream, which it would overlap; windows above
+ *              aed_seq_max always run in parallel.  Other values are rejected.
+ *   aed_seq_max  largest window the sequential AED takes (0 = 512; at most 1024) */
 typedef struct hqr_params {
     int ns, nw, nmin, nibble, kexsh;
     int64_t itmax;
@@ -66,6 +78,7 @@ typedef struct hqr_params {
     int streams;
     int small_shifts;
     int aed_ns, aed_nw, aed_nmin;
+    int aed_mode, aed_seq_max;
 } hqr_params;
 
 /* Process-wide defaults used by later calls.  Returns 0 or -1 (NULL / invalid). */
@@ -218,8 +231,9 @@ int hqr_eig_backward_batched(const double *T, const double *Q, const int64_t *of
  * stats[0] AED steps, [1] sweeps, [2] shifts used, [3] eigenvalues deflated by
  * AED, [4] small-solver calls, [5] host synchronizations, [6] kernel launches,
  * [7] chase windows, [8] deflation windows and [9] reordering windows of the
- * deflation checks of large AED windows.  Returns the number of entries
- * written (<= len, at most 10). */
+ * deflation checks of large AED windows, [10] sequential and [11] parallel
+ * AEDs of windows larger than 96.  Returns the number of entries written
+ * (<= len, at most 12). */
 int hqr_last_stats(int64_t *stats, int len);
 
 /* Kernel-class timing for measurement tools.  When enabled, the driver

@@ -42,10 +42,11 @@ def params() -> dict:
 
 
 def last_stats() -> dict:
-    arr = (ctypes.c_int64 * 10)()
-    lib().hqr_last_stats(arr, 10)
+    arr = (ctypes.c_int64 * 12)()
+    lib().hqr_last_stats(arr, 12)
     keys = ["aed_steps", "sweeps", "shifts", "aed_deflated", "small_solves", "host_syncs",
-            "launches", "chase_windows", "deflation_windows", "reordering_windows"]
+            "launches", "chase_windows", "deflation_windows", "reordering_windows",
+            "sequential_aeds", "parallel_aeds"]
     return dict(zip(keys, list(arr)))
 
 

@@ -187,6 +187,10 @@ hipError_t restore_blocked(double *T, int64_t ldt, int nw, int ns, double *Vw, i
                            double *ws, double *beta_dev, hipStream_t st);
 
 // ---- launchers (hqr_gemm.hip) ----
+// Sequential AED of a window copy (one workgroup): Schur form, spike test and
+// reordering of all candidates; the result in st (ns, nd, info).
+hipError_t launch_seq_aed(double *T, int w, double *V, double s, Defl dfl, int nwb, int nsb, IterStatus *st,
+                          hipStream_t strm);
 hipError_t launch_updates(const UpdBatch &b, hipStream_t s);
 void free_update_ws();
 // C = beta C + alpha op(A) op(B) (column major; op 1 = transposed), FP64 MFMA,

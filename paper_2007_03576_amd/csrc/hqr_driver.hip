@@ -69,7 +69,7 @@ int g_batched_wg_per_cu = 2, g_batched_wide_n = 320;
 // Per-bucket AED window and shift count of the batched form (empty: double
 // shifts for every order), chosen by the package's autotuner.
 BatchedTable g_btab = {0, {0}, {0}, {0}};
-constexpr int NSTATS = 10;
+constexpr int NSTATS = 12;
 thread_local int64_t t_stats[NSTATS];
 
 struct Params {
@@ -81,6 +81,8 @@ struct Params {
     int aed_ns, aed_nw, aed_nmin; // recursive solve of large AED windows (0 = automatic)
     int defl_mode;                // 0 LAPACK-style, 1 norm-stable, 2 fixed (Sec. 5.6)
     double defl_thold;            // threshold of the fixed conditions
+    int aed_mode;                 // large AED windows: 0 adaptive, 1 sequential, 2 parallel (Sec. 3.5)
+    int seq_max;                  // largest window of the sequential AED
 };
 
 // Reading of automatic parameters: LAPACK's documented shift-count table and
@@ -140,6 +142,16 @@ struct Workspace {
     int *flag = nullptr;
     hipEvent_t ev_pool[64];
     int ev_next = 0;
+    // update work queued on the deferred stream: one event per flush with its
+    // counted flops (a ring; the adaptive AED decision pops finished entries)
+    static constexpr int NPOOL = 32;
+    hipEvent_t pool_ev[NPOOL];
+    double pool_fl[NPOOL];
+    int pool_head = 0, pool_n = 0;
+    // sequential AED time model t = seq_a w^3 (seconds), refined from the
+    // measured sequential AEDs
+    hipEvent_t seq_t0 = nullptr, seq_t1 = nullptr;
+    double seq_a = 2.5e-9;
     bool init = false;
 };
 
@@ -265,6 +277,9 @@ int ensure_ws(Workspace &W, int dev)
     W.slot_used.assign(W.nslots, 0);
     for (int i = 0; i < W.nslots; ++i) CK(hipEventCreateWithFlags(&W.slot_ev[i], hipEventDisableTiming));
     for (int i = 0; i < 64; ++i) CK(hipEventCreateWithFlags(&W.ev_pool[i], hipEventDisableTiming));
+    for (int i = 0; i < Workspace::NPOOL; ++i) CK(hipEventCreateWithFlags(&W.pool_ev[i], hipEventDisableTiming));
+    CK(hipEventCreate(&W.seq_t0));
+    CK(hipEventCreate(&W.seq_t1));
     CK(hipMalloc(&W.flag, sizeof(int) * 4));
     W.init = true;
     return 0;
@@ -372,6 +387,17 @@ int flush(UpdBatch &b, hipStream_t s, Ctx &C)
         CK(launch_updates(b, s));
         prof_end(pid, s, fl, by);
         if (C.stats) C.stats[6]++;
+        Workspace &W = *C.W;
+        if (C.two && s == W.lo) {
+            if (W.pool_n == Workspace::NPOOL) { // ring full: forget the oldest entry
+                W.pool_head = (W.pool_head + 1) % Workspace::NPOOL;
+                W.pool_n--;
+            }
+            const int slot = (W.pool_head + W.pool_n) % Workspace::NPOOL;
+            CK(hipEventRecord(W.pool_ev[slot], s));
+            W.pool_fl[slot] = fl;
+            W.pool_n++;
+        }
     }
     b.njobs = 0;
     b.first_tile[0] = 0;
@@ -611,6 +637,23 @@ void progress_line(int ilo, int kbot, int nd)
 
 // AED step with a window larger than the LDS solver: recursive Schur form of
 // a copy of the window, corner deflation, Hessenberg restoration.
+// Update flops still queued on the deferred stream (finished flushes are
+// dropped by querying their events; no synchronization).
+double pool_pending(Workspace &W)
+{
+    while (W.pool_n > 0 && hipEventQuery(W.pool_ev[W.pool_head]) == hipSuccess) {
+        W.pool_head = (W.pool_head + 1) % Workspace::NPOOL;
+        W.pool_n--;
+    }
+    double fl = 0.0;
+    for (int i = 0; i < W.pool_n; ++i) fl += W.pool_fl[(W.pool_head + i) % Workspace::NPOOL];
+    return fl;
+}
+
+// Rate assumed for queued update work in the adaptive AED decision: the
+// update kernels' measured throughput on this GPU is 6..13 TFLOP/s.
+constexpr double POOL_RATE = 10e12;
+
 int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd, int &ns, int &ncand)
 {
     Workspace &W = *C.W;
@@ -625,104 +668,142 @@ int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd
     }
     double *T = W.wT[depth], *Vw = W.wV[depth], *Ut = W.wU[depth];
     CK(launch_window_copy(V.H, V.ld, kwtop, w, T, w, Vw, w, C.hi));
-    // Reading for the recursive solve of the window: AED windows of w/4
-    // (48..96, within the one-workgroup solver) and as many shifts per sweep
-    // as such a window delivers (at most w/4).  Measured at n = 16384 (AED
-    // windows of 1024): nw/4 shifts 48.8 s per solve, 64 shifts 29.7 s, nw
-    // shifts 27.3 s; at n = 4096 (windows of 256) no difference.
-    Params Pi = C.P;
-    Pi.nw = std::min(std::max(w / 4, 48), MMAX);
-    Pi.ns = std::max(2, Pi.nw & ~1);
-    if (C.P.aed_nw > 0) Pi.nw = C.P.aed_nw;
-    if (C.P.aed_ns > 0) Pi.ns = C.P.aed_ns;
-    if (C.P.aed_nmin > 0) Pi.nmin = C.P.aed_nmin;
-    Pi.ns = std::min(Pi.ns, std::max(2, (w / 4) & ~1));
-    Pi.itmax = C.P.itmax;
-    View Vi{T, w, w, Vw, w, w};
-    Ctx Ci = C;
-    Ci.two = false; // the window is small; keep its updates in order on one stream
-    int info = 0;
-    int rc = run(Ci, Vi, 0, w - 1, Pi, depth + 1, &info);
-    if (rc) return rc;
-    if (info > 0) {
-        nd = 0;
-        ns = w;
-        CK(launch_block_eigs(T, w, w, W.st_dev->cr, W.st_dev->ci, C.hi));
-        if (read_status(C, w)) return -1;
-        ncand = w;
-        return 0;
+    // Sequential or parallel AED (Sec. 3.5, "Adaptive approach").  The
+    // sequential AED runs on one workgroup, so it is preferred when it is
+    // predicted to finish while the deferred stream is still busy with queued
+    // updates that it overlaps; otherwise the window is solved in parallel.
+    bool seq = false;
+    if (w <= C.P.seq_max) {
+        if (C.P.aed_mode == 1) {
+            seq = true;
+        } else if (C.P.aed_mode == 0 && C.two) {
+            const double t_seq = W.seq_a * (double)w * (double)w * (double)w;
+            seq = t_seq <= pool_pending(W) / POOL_RATE;
+        }
     }
-    // Deflation check of the whole window (Sec. 3.5 "Parallel aggressive
-    // early deflation"): deflation windows of order <= 96 move up from the
-    // bottom corner.  Each examines its unchecked candidates bottom-up (the
-    // failures of the window below it, at its bottom, count as failed) and
-    // leaves all failures at its top; the next window ends at the bottommost
-    // failure.  When the failures fill more than half of a window (and at
-    // most two thirds), a chain of reordering windows carries them to the top
-    // of the AED window and the next deflation window starts at the next
-    // unevaluated candidate; with more failures the rest of the window counts
-    // as undeflated (few of its candidates would deflate).  The
-    // transformation of each window updates the window rows to its right,
-    // the rows above it and V.  A rejected swap halts the check (the greedy
-    // rule): everything above the deflated bottom then counts as undeflated.
-    int bot = w, nfail = 0, ntop = 0;
-    auto window = [&](int wbot, int wd, int nforced, int reorder, int &c0, int &wdd, int &halted,
-                      int &nsr) -> int {
-        int slc = take_slot(C);
-        double *Utc = slot_ptr(W, slc); // used on the critical stream only
-        int pidc = prof_begin(3, C.hi);
-        CK(launch_corner_deflate(T, w, wbot, wd, Vw, w, s, C.dfl, Utc, W.st_dev, nforced, reorder, C.hi));
-        prof_end(pidc, C.hi, 0.0, 0.0);
-        if (C.stats) C.stats[reorder ? 9 : 8]++;
+    int bot = w;
+    if (seq) {
+        const int nwb = std::min(64, std::max(24, w / 4)), nsb = std::min(64, std::max(2, w / 4)) & ~1;
+        int pids = prof_begin(3, C.hi);
+        CK(hipEventRecord(W.seq_t0, C.hi));
+        CK(launch_seq_aed(T, w, Vw, s, C.dfl, nwb, nsb, W.st_dev, C.hi));
+        CK(hipEventRecord(W.seq_t1, C.hi));
+        prof_end(pids, C.hi, 10.0 * (double)w * w * w, 0.0);
+        if (C.stats) C.stats[10]++;
         if (read_status(C, 0)) return -1;
-        c0 = W.st_host->kwtop;
-        wdd = W.st_host->nw;
-        halted = W.st_host->info;
-        nsr = W.st_host->ns; // undeflated leading rows of the AED window
-        UpdBatch b = make_batch();
-        add_job(b, T + (int64_t)c0 * w, w, c0, wdd, Utc, 0);
-        add_job(b, T + c0 + (int64_t)wbot * w, w, w - wbot, wdd, Utc, 1);
-        add_job(b, Vw + (int64_t)c0 * w, w, w, wdd, Utc, 0);
-        if (flush(b, C.hi, C)) return -1;
-        return 0;
-    };
-    for (;;) {
-        const int wd = std::min(bot - ntop, MMAX); // the failures already at the top stay out
-        if (wd <= nfail) break;
-        int c0, wdd, halted, nsr;
-        const int rw = window(bot, wd, nfail, 0, c0, wdd, halted, nsr);
-        if (rw) return rw;
-        const int nf = nsr - c0; // failures now at [c0, nsr), deflated below
-        bot = nsr;
-        if (halted || c0 <= ntop) break;
-        if (2 * nf <= wdd) {
-            nfail = nf;
-            continue;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, W.seq_t0, W.seq_t1) == hipSuccess && ms > 0.0f)
+            W.seq_a = 0.5 * W.seq_a + 0.5 * (1e-3 * ms / ((double)w * w * w));
+        if (W.st_host->info > 0) { // the window did not converge: discard it
+            nd = 0;
+            ns = w;
+            CK(launch_block_eigs(T, w, w, W.st_dev->cr, W.st_dev->ci, C.hi));
+            if (read_status(C, w)) return -1;
+            ncand = w;
+            return 0;
         }
-        // a reordering window advances by its order minus the failures it
-        // carries: beyond two thirds of a window the rest is left unevaluated
-        if (3 * nf > 2 * wdd) break;
-        // reordering chain: failures [fb - nf, fb) up to [ntop, ntop + nf)
-        int fb = nsr;
-        bool moved = true;
-        while (fb - nf > ntop) {
-            const int wr = std::min(fb - ntop, MMAX);
-            if (wr <= nf + 1) {
-                moved = false; // no room to pass a block
-                break;
-            }
-            int c0r, wdr, haltedr, nsrr;
-            const int rr = window(fb, wr, nf, 1, c0r, wdr, haltedr, nsrr);
-            if (rr) return rr;
-            if (haltedr || c0r + nf >= fb) {
-                moved = false;
-                break;
-            }
-            fb = c0r + nf;
+        bot = W.st_host->ns;
+    } else {
+        if (C.stats) C.stats[11]++;
+        // Reading for the recursive solve of the window: AED windows of w/4
+        // (48..96, within the one-workgroup solver) and as many shifts per sweep
+        // as such a window delivers (at most w/4).  Measured at n = 16384 (AED
+        // windows of 1024): nw/4 shifts 48.8 s per solve, 64 shifts 29.7 s, nw
+        // shifts 27.3 s; at n = 4096 (windows of 256) no difference.
+        Params Pi = C.P;
+        Pi.nw = std::min(std::max(w / 4, 48), MMAX);
+        Pi.ns = std::max(2, Pi.nw & ~1);
+        if (C.P.aed_nw > 0) Pi.nw = C.P.aed_nw;
+        if (C.P.aed_ns > 0) Pi.ns = C.P.aed_ns;
+        if (C.P.aed_nmin > 0) Pi.nmin = C.P.aed_nmin;
+        Pi.ns = std::min(Pi.ns, std::max(2, (w / 4) & ~1));
+        Pi.itmax = C.P.itmax;
+        View Vi{T, w, w, Vw, w, w};
+        Ctx Ci = C;
+        Ci.two = false; // the window is small; keep its updates in order on one stream
+        int info = 0;
+        int rc = run(Ci, Vi, 0, w - 1, Pi, depth + 1, &info);
+        if (rc) return rc;
+        if (info > 0) {
+            nd = 0;
+            ns = w;
+            CK(launch_block_eigs(T, w, w, W.st_dev->cr, W.st_dev->ci, C.hi));
+            if (read_status(C, w)) return -1;
+            ncand = w;
+            return 0;
         }
-        if (!moved) break;
-        ntop += nf;
-        nfail = 0;
+        // Deflation check of the whole window (Sec. 3.5 "Parallel aggressive
+        // early deflation"): deflation windows of order <= 96 move up from the
+        // bottom corner.  Each examines its unchecked candidates bottom-up (the
+        // failures of the window below it, at its bottom, count as failed) and
+        // leaves all failures at its top; the next window ends at the bottommost
+        // failure.  When the failures fill more than half of a window (and at
+        // most two thirds), a chain of reordering windows carries them to the top
+        // of the AED window and the next deflation window starts at the next
+        // unevaluated candidate; with more failures the rest of the window counts
+        // as undeflated (few of its candidates would deflate).  The
+        // transformation of each window updates the window rows to its right,
+        // the rows above it and V.  A rejected swap halts the check (the greedy
+        // rule): everything above the deflated bottom then counts as undeflated.
+        int nfail = 0, ntop = 0;
+        auto window = [&](int wbot, int wd, int nforced, int reorder, int &c0, int &wdd, int &halted,
+                          int &nsr) -> int {
+            int slc = take_slot(C);
+            double *Utc = slot_ptr(W, slc); // used on the critical stream only
+            int pidc = prof_begin(3, C.hi);
+            CK(launch_corner_deflate(T, w, wbot, wd, Vw, w, s, C.dfl, Utc, W.st_dev, nforced, reorder, C.hi));
+            prof_end(pidc, C.hi, 0.0, 0.0);
+            if (C.stats) C.stats[reorder ? 9 : 8]++;
+            if (read_status(C, 0)) return -1;
+            c0 = W.st_host->kwtop;
+            wdd = W.st_host->nw;
+            halted = W.st_host->info;
+            nsr = W.st_host->ns; // undeflated leading rows of the AED window
+            UpdBatch b = make_batch();
+            add_job(b, T + (int64_t)c0 * w, w, c0, wdd, Utc, 0);
+            add_job(b, T + c0 + (int64_t)wbot * w, w, w - wbot, wdd, Utc, 1);
+            add_job(b, Vw + (int64_t)c0 * w, w, w, wdd, Utc, 0);
+            if (flush(b, C.hi, C)) return -1;
+            return 0;
+        };
+        for (;;) {
+            const int wd = std::min(bot - ntop, MMAX); // the failures already at the top stay out
+            if (wd <= nfail) break;
+            int c0, wdd, halted, nsr;
+            const int rw = window(bot, wd, nfail, 0, c0, wdd, halted, nsr);
+            if (rw) return rw;
+            const int nf = nsr - c0; // failures now at [c0, nsr), deflated below
+            bot = nsr;
+            if (halted || c0 <= ntop) break;
+            if (2 * nf <= wdd) {
+                nfail = nf;
+                continue;
+            }
+            // a reordering window advances by its order minus the failures it
+            // carries: beyond two thirds of a window the rest is left unevaluated
+            if (3 * nf > 2 * wdd) break;
+            // reordering chain: failures [fb - nf, fb) up to [ntop, ntop + nf)
+            int fb = nsr;
+            bool moved = true;
+            while (fb - nf > ntop) {
+                const int wr = std::min(fb - ntop, MMAX);
+                if (wr <= nf + 1) {
+                    moved = false; // no room to pass a block
+                    break;
+                }
+                int c0r, wdr, haltedr, nsrr;
+                const int rr = window(fb, wr, nf, 1, c0r, wdr, haltedr, nsrr);
+                if (rr) return rr;
+                if (haltedr || c0r + nf >= fb) {
+                    moved = false;
+                    break;
+                }
+                fb = c0r + nf;
+            }
+            if (!moved) break;
+            ntop += nf;
+            nfail = 0;
+        }
     }
     ns = bot;
     nd = w - bot;
@@ -975,6 +1056,7 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
 // threshold >= 0).
 bool defl_ok(const hqr_params *p)
 {
+    if (p->aed_mode < 0 || p->aed_mode > 2 || p->aed_seq_max < 0) return false;
     if (p->defl_mode == 0 || p->defl_mode == 1) return true;
     return p->defl_mode == 2 && p->defl_thold >= 0.0 && std::isfinite(p->defl_thold);
 }
@@ -1008,6 +1090,8 @@ Params resolve(const hqr_params *pp, int n)
     P.nw = std::min(P.nw, MAX_UPDATE_K);
     P.defl_mode = p.defl_mode;
     P.defl_thold = p.defl_thold;
+    P.aed_mode = p.aed_mode;
+    P.seq_max = p.aed_seq_max > 0 ? std::min(p.aed_seq_max, MAX_UPDATE_K) : 512;
     return P;
 }
 
@@ -1201,6 +1285,9 @@ int hqr_finalize(void)
         hipDeviceSynchronize();
         for (auto e : W.slot_ev) hipEventDestroy(e);
         for (int i = 0; i < 64; ++i) hipEventDestroy(W.ev_pool[i]);
+        for (int i = 0; i < Workspace::NPOOL; ++i) hipEventDestroy(W.pool_ev[i]);
+        hipEventDestroy(W.seq_t0);
+        hipEventDestroy(W.seq_t1);
         hipStreamDestroy(W.lo);
         hipFree(W.st_dev);
         hipHostFree(W.st_host);

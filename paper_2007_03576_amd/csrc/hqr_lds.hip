@@ -3098,6 +3098,56 @@ __global__ void __launch_bounds__(NT) k_batched_aed(double *H, double *Q, const 
     }
 }
 
+// Sequential AED of a window too large for the LDS solver (Sec. 3.5,
+// "Adaptive approach": the variant one worker runs alone): one workgroup
+// reduces the window copy T (order w, leading dimension w, zeros below the
+// subdiagonal) to Schur form with V (= I on entry) accumulating, by the
+// batched form's per-matrix solver (its own small AED windows in LDS, nwb and
+// nsb), then examines every candidate bottom-up against the spike s V(0, :)
+// and moves the failures to the top (the pipelined reordering, here in global
+// memory).  st->ns = undeflated leading rows, st->nd = w - ns, st->info > 0
+// when the Schur reduction stopped at its iteration limit (the rows above it
+// then count as undeflated).
+__global__ void __launch_bounds__(NT) k_seq_aed(double *T, int w, double *V, double s, Defl dfl, int nwb, int nsb,
+                                                IterStatus *st)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    SmemB &S = *reinterpret_cast<SmemB *>(smem_raw);
+    if (threadIdx.x == 0) {
+        S.flops = 0.0;
+        S.nphase = S.nbstep = S.nswap = S.nrphase = 0;
+    }
+    __syncthreads();
+    const int info = batched_aed_solve(S, T, w, V, nwb, nsb, dfl);
+    __syncthreads();
+    const int ns = aed_deflate(S, T, w, w, V, w, w, 0, s, info > 0 ? info : 0, dfl);
+    if (threadIdx.x == 0) {
+        st->ns = ns;
+        st->nd = w - ns;
+        st->info = info;
+        st->kwtop = 0;
+        st->nw = w;
+        st->nswap = S.nswap;
+        st->nrphase = S.nrphase;
+    }
+}
+
+hipError_t launch_seq_aed(double *T, int w, double *V, double s, Defl dfl, int nwb, int nsb, IterStatus *st,
+                          hipStream_t strm)
+{
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_seq_aed, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)sizeof(SmemB));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    nwb = std::min(std::max(nwb, 8), BWIN);
+    nsb = std::max(2, nsb & ~1);
+    hipLaunchKernelGGL(k_seq_aed, dim3(1), dim3(NT), sizeof(SmemB), strm, T, w, V, s, dfl, nwb, nsb, st);
+    return hipGetLastError();
+}
+
 hipError_t launch_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int batch, double *wr,
                           double *wi, const int64_t *eoff, int32_t *info, int32_t *queue, int wg_per_cu, int wide_n,
                           const BatchedTable &tab, hipStream_t s)

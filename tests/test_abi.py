@@ -65,6 +65,11 @@ def test_params_roundtrip_and_rejection(L):
         hp = HqrParams()
         hp.defl_mode, hp.defl_thold = mode, thold
         assert L.hqr_set_params(ctypes.byref(hp)) == rc, (mode, thold)
+    # large-window AED mode: 0 adaptive, 1 sequential, 2 parallel; a window limit >= 0
+    for mode, lim, rc in [(0, 0, 0), (1, 256, 0), (2, 0, 0), (3, 0, -1), (-1, 0, -1), (1, -5, -1)]:
+        hp = HqrParams()
+        hp.aed_mode, hp.aed_seq_max = mode, lim
+        assert L.hqr_set_params(ctypes.byref(hp)) == rc, (mode, lim)
     assert L.hqr_set_params(ctypes.byref(old)) == 0
     assert L.hqr_set_params(None) == -1
 

@@ -120,14 +120,50 @@ def test_big_aed_reordering_chains(gpu):
 
 
 def test_large_window_factor(gpu):
-    # an AED window of 1024: its factor (order 1024) is applied by the update
-    # kernel with the whole 1024-long panel of each tile staged in LDS
+    # an AED window of 1024: its factor (order 1024) is applied out of place
+    # by the tiled MFMA product and copied back
     _say("case AED window 1024 n=1300 ns=64")
     H = hi.gaussian_hessenberg(1300, seed=31)
     T, Q, w, info, st = run_gpu(H, {"ns": 64, "nw": 1024})
     _say(f"stats {st}")
     assert info == 0
     assert_schur(H, T, Q, w, tag="win1024")
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_aed_modes(gpu, mode):
+    # Sec. 3.5, adaptive approach: AED windows above 96 run sequentially (one
+    # workgroup reduces the window, tests every candidate and reorders the
+    # failures) or in parallel (recursive solve, chains of deflation and
+    # reordering windows); 0 decides per window from the queued update work
+    total = {"sequential_aeds": 0, "parallel_aeds": 0}
+    for n, seed, nw in [(600, 21, 192), (500, 22, 128), (700, 23, 320)]:
+        _say(f"case AED mode {mode} n={n} nw={nw} seed={seed}")
+        H = hi.hessrand(n, seed=seed)
+        T, Q, w, info, st = run_gpu(H, {"ns": 32, "nw": nw, "aed_mode": mode})
+        _say(f"stats {st}")
+        assert info == 0
+        assert_schur(H, T, Q, w, tag=f"aedmode{mode}_{n}")
+        for k in total:
+            total[k] += st[k]
+    assert total["sequential_aeds"] + total["parallel_aeds"] > 0
+    if mode == 1:
+        assert total["parallel_aeds"] == 0
+    if mode == 2:
+        assert total["sequential_aeds"] == 0
+
+
+def test_sequential_aed_size_limit(gpu):
+    # windows above aed_seq_max go to the parallel AED even when the
+    # sequential one is requested (the smaller windows of a nearly deflated
+    # active block may still run sequentially)
+    _say("case sequential AED limit n=600 nw=192 aed_seq_max=160")
+    H = hi.hessrand(600, seed=24)
+    T, Q, w, info, st = run_gpu(H, {"ns": 32, "nw": 192, "aed_mode": 1, "aed_seq_max": 160})
+    _say(f"stats {st}")
+    assert info == 0
+    assert_schur(H, T, Q, w, tag="seqlimit")
+    assert st["parallel_aeds"] > 0
 
 
 @pytest.mark.parametrize("nsmall", [8, 16])
