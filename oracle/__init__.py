@@ -38,6 +38,7 @@ def lib():
         L.hqr_oracle_aed.argtypes = [dp, dp, i64, i64, i64, i64, ctypes.c_int, dp, dp,
                                      ctypes.POINTER(ctypes.c_int)]
         L.hqr_oracle_eig_backward.argtypes = [dp, dp, i64, i64, dp, dp, dp, dp, dp, ctypes.c_int]
+        L.hqr_oracle_qz.argtypes = [dp, dp, dp, dp, i64, i64, dp, dp, dp, i64]
         L.hqr_oracle_set_mutation.argtypes = [ctypes.c_int]
         L.hqr_oracle_set_mutation.restype = None
         L.hqr_oracle_force_swap_failure.argtypes = [ctypes.c_int]
@@ -83,6 +84,24 @@ def schur(H, want_q=True, Q0=None, ns=0, nw=0, nmin=0, itmax=0, defl_mode=0, def
     info = lib().hqr_oracle_schur_defl(_p(T), _p(Q), n, max(n, 1), _p(wr), _p(wi), ns, nw, nmin,
                                        itmax, st, int(defl_mode), float(defl_thold))
     return T, Q, (wr + 1j * wi)[:n], info, list(st)
+
+
+def qz(H, T, want_qz=True, itmax=0):
+    """Generalized real Schur form of the Hessenberg-triangular pair (H, T):
+    returns (S, Tt, Q, Z, alpha, beta, info) with Q^T H Z = S, Q^T T Z = Tt,
+    alpha complex and beta >= 0 in diagonal order (beta = 0: infinite)."""
+    S = _fortran(H)
+    Tt = _fortran(T)
+    n = S.shape[0]
+    Q = Z = None
+    if want_qz:
+        Q = np.asfortranarray(np.eye(n))
+        Z = np.asfortranarray(np.eye(n))
+    ar = np.zeros(max(n, 1))
+    ai = np.zeros(max(n, 1))
+    be = np.zeros(max(n, 1))
+    info = lib().hqr_oracle_qz(_p(S), _p(Tt), _p(Q), _p(Z), n, max(n, 1), _p(ar), _p(ai), _p(be), int(itmax))
+    return S, Tt, Q, Z, (ar + 1j * ai)[:n], be[:n], info
 
 
 def sweep(H, Q, ktop, kbot, shifts, vigilant=False):

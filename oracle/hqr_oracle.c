@@ -1268,3 +1268,289 @@ int hqr_oracle_eig_backward(const double *T, const double *Q, int64_t n64, int64
     free(cf);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* The QZ variant (Sec. 2, remarks on the generalized case; Sec. 3.2 'push    */
+/* infinities'): double implicit shift QZ on a Hessenberg-triangular pair.    */
+/* Every transformation is applied to the full rows and columns of H and T.   */
+/* ------------------------------------------------------------------------- */
+
+/* Reflector P = I - tau v v^T, v[m-1] = 1, with x^T P = beta e_{m-1}^T: the
+   Householder reflector of the reversed vector, reversed. */
+static void house_last(int m, const double *x, double *v, double *tau, double *beta)
+{
+    double xr[3], vr[3];
+    for (int i = 0; i < m; ++i) xr[i] = x[m - 1 - i];
+    house(m, xr, vr, tau, beta);
+    for (int i = 0; i < m; ++i) v[i] = vr[m - 1 - i];
+}
+
+/* Rotation zeroing the second entry of (a, b): c = a/r, s = b/r. */
+static void qz_rot(double a, double b, double *c, double *s)
+{
+    double r = hypot(a, b);
+    if (r == 0.0) {
+        *c = 1.0;
+        *s = 0.0;
+    } else {
+        *c = a / r;
+        *s = b / r;
+    }
+}
+
+/* rows p, p+1 of A (all columns) <- G rows, G = [[c, s], [-s, c]] */
+static void qz_rows(double *A, long ld, int n, int p, double c, double s)
+{
+    for (int j = 0; j < n; ++j) {
+        double x = A[IX(p, j, ld)], y = A[IX(p + 1, j, ld)];
+        A[IX(p, j, ld)] = c * x + s * y;
+        A[IX(p + 1, j, ld)] = -s * x + c * y;
+    }
+}
+
+/* columns a, b of A (all rows): col a <- c col a + s col b, col b <- -s col a + c col b */
+static void qz_cols(double *A, long ld, int n, int a, int b, double c, double s)
+{
+    if (A == NULL) return;
+    for (int i = 0; i < n; ++i) {
+        double x = A[IX(i, a, ld)], y = A[IX(i, b, ld)];
+        A[IX(i, a, ld)] = c * x + s * y;
+        A[IX(i, b, ld)] = -s * x + c * y;
+    }
+}
+
+/* Left rotation on rows p, p+1 of H and T, accumulated into Q (Q <- Q G^T). */
+static void qz_left(double *H, double *T, double *Q, long ld, int n, int p, double c, double s)
+{
+    qz_rows(H, ld, n, p, c, s);
+    if (g_mut != 22) qz_rows(T, ld, n, p, c, s);
+    qz_cols(Q, ld, n, p, p + 1, c, s);
+}
+
+/* Right rotation on columns a, b of H, T and Z. */
+static void qz_right(double *H, double *T, double *Z, long ld, int n, int a, int b, double c, double s)
+{
+    qz_cols(H, ld, n, a, b, c, s);
+    qz_cols(T, ld, n, a, b, c, s);
+    qz_cols(Z, ld, n, a, b, c, s);
+}
+
+/* An infinite eigenvalue at T[j,j] = 0 inside the block [l, i] is chased to
+   the top of the block and deflated there (the 'push infinities' task chases
+   them up the diagonal with rotations).  Each step moves the zero from j to
+   j-1 with a right rotation on columns (j-1, j) that zeroes T[j-1,j-1], and
+   removes the fill H[j+1,j-1] this leaves with a left rotation on rows
+   (j, j+1).  At the top, a left rotation on rows (l, l+1) zeroes H[l+1,l]:
+   the 1x1 block l (with T[l,l] = 0) decouples. */
+static void qz_push_up(double *H, double *T, double *Q, double *Z, long ld, int n, int l, int i, int j)
+{
+    double c, s;
+    for (int jc = j; jc > l; --jc) {
+        qz_rot(T[IX(jc - 1, jc, ld)], T[IX(jc - 1, jc - 1, ld)], &c, &s);
+        qz_right(H, T, Z, ld, n, jc, jc - 1, c, s);
+        T[IX(jc - 1, jc - 1, ld)] = 0.0;
+        if (jc + 1 <= i) {
+            qz_rot(H[IX(jc, jc - 1, ld)], H[IX(jc + 1, jc - 1, ld)], &c, &s);
+            qz_left(H, T, Q, ld, n, jc, c, s);
+            H[IX(jc + 1, jc - 1, ld)] = 0.0;
+        }
+    }
+    qz_rot(H[IX(l, l, ld)], H[IX(l + 1, l, ld)], &c, &s);
+    qz_left(H, T, Q, ld, n, l, c, s);
+    H[IX(l + 1, l, ld)] = 0.0;
+}
+
+/* Generalized eigenvalues of the 2x2 pair (A, B) at rows/columns k, k+1
+   (B upper triangular, nonsingular): the eigenvalues of A B^{-1}. */
+static void qz_eig2(const double *H, const double *T, long ld, int k, double *r1, double *i1, double *r2,
+                    double *i2)
+{
+    double a11 = H[IX(k, k, ld)], a12 = H[IX(k, k + 1, ld)], a21 = H[IX(k + 1, k, ld)], a22 = H[IX(k + 1, k + 1, ld)];
+    double b11 = T[IX(k, k, ld)], b12 = T[IX(k, k + 1, ld)], b22 = T[IX(k + 1, k + 1, ld)];
+    /* B^{-1} = [[1/b11, -b12/(b11 b22)], [0, 1/b22]] */
+    double m11 = a11 / b11, m21 = a21 / b11;
+    double m12 = (a12 - m11 * b12) / b22, m22 = (a22 - m21 * b12) / b22;
+    eig2(m11, m12, m21, m22, r1, i1, r2, i2);
+}
+
+/* A 2x2 block at k, k+1 whose pair has real eigenvalues is split: a right
+   rotation whose first column spans the null space of A - lambda B, then a
+   left rotation making the first column of B Z triangular; both pairs'
+   (k+1, k) entries become zero. */
+static void qz_split2(double *H, double *T, double *Q, double *Z, long ld, int n, int k, double lam)
+{
+    double m11 = H[IX(k, k, ld)] - lam * T[IX(k, k, ld)], m12 = H[IX(k, k + 1, ld)] - lam * T[IX(k, k + 1, ld)];
+    double m21 = H[IX(k + 1, k, ld)], m22 = H[IX(k + 1, k + 1, ld)] - lam * T[IX(k + 1, k + 1, ld)];
+    /* null vector (z1, z2) of M from its larger row */
+    double z1, z2;
+    if (hypot(m11, m12) >= hypot(m21, m22)) {
+        z1 = -m12;
+        z2 = m11;
+    } else {
+        z1 = -m22;
+        z2 = m21;
+    }
+    double c, s;
+    qz_rot(z1, z2, &c, &s);
+    if (c == 1.0 && s == 0.0 && z1 == 0.0 && z2 == 0.0) return;
+    /* columns (k, k+1): new col k = c col k + s col k+1 (first column = (c, s) ~ (z1, z2)) */
+    qz_right(H, T, Z, ld, n, k, k + 1, c, s);
+    qz_rot(T[IX(k, k, ld)], T[IX(k + 1, k, ld)], &c, &s);
+    qz_left(H, T, Q, ld, n, k, c, s);
+    H[IX(k + 1, k, ld)] = 0.0;
+    T[IX(k + 1, k, ld)] = 0.0;
+}
+
+/* One double-shift QZ sweep over the block [l, i] (i - l >= 2) with the
+   shifts (re1 + i im1, re2 + i im2) (a conjugate pair or two reals).  The
+   first column of (H T^{-1} - s1)(H T^{-1} - s2) on rows l..l+2 gives the
+   reflector that introduces the bulge; at each position k a 3x3 reflector
+   from the left (rows k+1..k+3) moves the bulge of H down, and two
+   reflectors from the right restore T: one from row k+3 of T (columns
+   k+1..k+3 mapped to the last column) and one from row k+2 (columns k+1..k+2). */
+static void qz_sweep(double *H, double *T, double *Q, double *Z, long ld, int n, int l, int i, double re1,
+                     double im1, double re2, double im2)
+{
+    const double sum = re1 + re2, prod = (g_mut == 23) ? -(re1 * re2 - im1 * im2) : re1 * re2 - im1 * im2;
+    const double t11 = T[IX(l, l, ld)], t12 = T[IX(l, l + 1, ld)], t22 = T[IX(l + 1, l + 1, ld)];
+    const double h11 = H[IX(l, l, ld)], h21 = H[IX(l + 1, l, ld)], h12 = H[IX(l, l + 1, ld)];
+    const double h22 = H[IX(l + 1, l + 1, ld)], h32 = H[IX(l + 2, l + 1, ld)];
+    /* N e1 with N = H T^{-1}, then y = T^{-1} N e1 and N^2 e1 = H y */
+    const double ne0 = h11 / t11, ne1 = h21 / t11;
+    const double y2 = ne1 / t22, y1 = (ne0 - t12 * y2) / t11;
+    double x[3];
+    x[0] = h11 * y1 + h12 * y2 - sum * ne0 + prod;
+    x[1] = h21 * y1 + h22 * y2 - sum * ne1;
+    x[2] = h32 * y2;
+    for (int k = l - 1; k <= i - 2; ++k) {
+        const int m = (i - k < 3) ? i - k : 3;
+        double v[3], tau, beta;
+        if (k >= l) {
+            for (int r = 0; r < m; ++r) x[r] = H[IX(k + 1 + r, k, ld)];
+        }
+        house(m, x, v, &tau, &beta);
+        refl_left(H, ld, k + 1, m, v, tau, 0, n - 1);
+        refl_left(T, ld, k + 1, m, v, tau, 0, n - 1);
+        if (Q) refl_right(Q, ld, k + 1, m, v, tau, 0, n - 1);
+        if (k >= l) {
+            H[IX(k + 1, k, ld)] = beta;
+            for (int r = 1; r < m; ++r) H[IX(k + 1 + r, k, ld)] = 0.0;
+        }
+        /* restore T: row k+m first (columns k+1..k+m onto the last), then row k+m-1 */
+        double w[3], tw, bw;
+        for (int r = 0; r < m; ++r) w[r] = T[IX(k + m, k + 1 + r, ld)];
+        house_last(m, w, v, &tw, &bw);
+        refl_right(H, ld, k + 1, m, v, tw, 0, n - 1);
+        refl_right(T, ld, k + 1, m, v, tw, 0, n - 1);
+        if (Z) refl_right(Z, ld, k + 1, m, v, tw, 0, n - 1);
+        for (int r = 0; r < m - 1; ++r) T[IX(k + m, k + 1 + r, ld)] = 0.0;
+        if (m == 3) {
+            for (int r = 0; r < 2; ++r) w[r] = T[IX(k + 2, k + 1 + r, ld)];
+            house_last(2, w, v, &tw, &bw);
+            refl_right(H, ld, k + 1, 2, v, tw, 0, n - 1);
+            refl_right(T, ld, k + 1, 2, v, tw, 0, n - 1);
+            if (Z && g_mut != 21) refl_right(Z, ld, k + 1, 2, v, tw, 0, n - 1);
+            T[IX(k + 2, k + 1, ld)] = 0.0;
+        }
+    }
+}
+
+int hqr_oracle_qz(double *H, double *T, double *Q, double *Z, int64_t n64, int64_t ld64, double *alphar,
+                  double *alphai, double *beta, int64_t itmax)
+{
+    const int n = (int)n64;
+    const long ld = (long)ld64;
+    if (n < 0 || ld < (n > 1 ? n : 1) || !H || !T) return -1;
+    if (n == 0) return 0;
+    if (itmax <= 0) itmax = 30 * (int64_t)(n > 10 ? n : 10);
+    double tn = 0.0;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i <= j; ++i) tn = hypot(tn, T[IX(i, j, ld)]);
+    /* Reading: the paper adopts LAPACK's convention |t_kk| <= u ||T||_F for
+       an infinite eigenvalue; the subdiagonal test of H is the conventional
+       |h_{k,k-1}| <= u (|h_{k-1,k-1}| + |h_kk|) with floor nu n / u. */
+    const double btol = U * tn, smlnum = DBL_MIN * ((double)n / U);
+    for (int k = 0; k < n; ++k)
+        if (fabs(T[IX(k, k, ld)]) <= btol) T[IX(k, k, ld)] = 0.0;
+    int i = n - 1, its = 0;
+    int64_t it = 0;
+    while (i >= 0) {
+        int l = i;
+        while (l > 0) {
+            double h = fabs(H[IX(l, l - 1, ld)]);
+            double tst = fabs(H[IX(l - 1, l - 1, ld)]) + fabs(H[IX(l, l, ld)]);
+            if (h <= dmax(smlnum, U * tst)) {
+                H[IX(l, l - 1, ld)] = 0.0;
+                break;
+            }
+            --l;
+        }
+        int kz = -1;
+        for (int k = l; k <= i; ++k)
+            if (T[IX(k, k, ld)] == 0.0) {
+                kz = k;
+                break;
+            }
+        if (kz >= 0 && l < i) {
+            qz_push_up(H, T, Q, Z, ld, n, l, i, kz);
+            /* the rotations change diagonal entries of T: re-apply the threshold below l */
+            for (int k = l + 1; k <= i; ++k)
+                if (fabs(T[IX(k, k, ld)]) <= btol) T[IX(k, k, ld)] = 0.0;
+            its = 0;
+            continue;
+        }
+        if (l == i) {
+            double a = H[IX(i, i, ld)], b = T[IX(i, i, ld)];
+            if (b < 0.0) {
+                a = -a;
+                b = -b;
+            }
+            alphar[i] = a;
+            alphai[i] = 0.0;
+            beta[i] = b;
+            --i;
+            its = 0;
+            continue;
+        }
+        if (l == i - 1) {
+            double r1, i1, r2, i2;
+            qz_eig2(H, T, ld, i - 1, &r1, &i1, &r2, &i2);
+            if (i1 == 0.0) {
+                qz_split2(H, T, Q, Z, ld, n, i - 1, r1);
+                continue; /* two 1x1 blocks now */
+            }
+            alphar[i - 1] = r1;
+            alphai[i - 1] = fabs(i1);
+            beta[i - 1] = 1.0;
+            alphar[i] = r2;
+            alphai[i] = -fabs(i1);
+            beta[i] = 1.0;
+            i -= 2;
+            its = 0;
+            continue;
+        }
+        if (it >= itmax) return i + 1;
+        double r1, i1, r2, i2;
+        if (its == 10 || its == 20) {
+            /* exceptional shifts: a real double shift off the bottom entries */
+            double ss = fabs(H[IX(i, i - 1, ld)] / T[IX(i - 1, i - 1, ld)]) +
+                        fabs(H[IX(i - 1, i - 2, ld)] / T[IX(i - 2, i - 2, ld)]);
+            r1 = r2 = H[IX(i, i, ld)] / T[IX(i, i, ld)] + 0.75 * ss;
+            i1 = i2 = 0.0;
+        } else {
+            qz_eig2(H, T, ld, i - 1, &r1, &i1, &r2, &i2);
+            if (i1 == 0.0) {
+                /* two real shifts: both at the one closer to the bottom ratio */
+                double tb = H[IX(i, i, ld)] / T[IX(i, i, ld)];
+                double pick = (fabs(r1 - tb) <= fabs(r2 - tb)) ? r1 : r2;
+                r1 = r2 = pick;
+            }
+        }
+        qz_sweep(H, T, Q, Z, ld, n, l, i, r1, i1, r2, i2);
+        for (int k = l; k <= i; ++k)
+            if (fabs(T[IX(k, k, ld)]) <= btol) T[IX(k, k, ld)] = 0.0;
+        ++it;
+        ++its;
+    }
+    return 0;
+}

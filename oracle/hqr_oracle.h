@@ -76,6 +76,22 @@ int hqr_oracle_eig_backward(const double *T, const double *Q, int64_t n, int64_t
                             const double *wr, const double *wi, const double *gwr,
                             const double *gwi, double *dH, int hess_mask);
 
+/* Generalized real Schur form of a Hessenberg-triangular pair (the QZ
+   variant: Sec. 2 remarks on the generalized case; Sec. 3.2 'push
+   infinities'): H (upper Hessenberg) and T (upper triangular), n x n,
+   leading dimension ld, column major, are overwritten by S = Q^T H Z (quasi
+   upper triangular, 2x2 blocks only for complex pairs) and Q^T T Z (upper
+   triangular); Q and Z (may be NULL) are multiplied from the right.  The
+   generalized eigenvalues (alphar + i alphai) / beta go to the three arrays
+   in diagonal order (beta >= 0; beta = 0 is an infinite eigenvalue).  Double
+   implicit shift QZ with 3x3 reflectors from the left and right reflectors
+   restoring T; diagonal entries of T with |t_kk| <= u ||T||_F are set to
+   zero and the infinite eigenvalue is chased to the top of its block by
+   rotations and deflated there.  itmax <= 0: 30 max(10, n) iterations.
+   Returns 0, or 1 + the bottom row of the block that did not converge. */
+int hqr_oracle_qz(double *H, double *T, double *Q, double *Z, int64_t n, int64_t ld, double *alphar,
+                  double *alphai, double *beta, int64_t itmax);
+
 /* Test hook: plants one deliberate mistake (see the mutation list in the
    source) so that tests can show the pins catch it.  0 = none. */
 void hqr_oracle_set_mutation(int m);
