@@ -5,9 +5,9 @@ HIP kernels; this package only marshals torch device tensors and streams.
 """
 from .api import (BatchedGraph, BatchedProblem, HqrError, batched_launch, eigenvectors, eigvals, hessenberg,
                   last_stats, params, schur, schur_batched, schur_colmajor, set_batched_launch, set_params,
-                  set_batched_table, batched_table)
+                  set_batched_table, batched_table, qz_batched)
 
 __all__ = ["schur", "schur_colmajor", "schur_batched", "eigvals", "hessenberg", "eigenvectors", "set_params", "params",
            "set_batched_table", "batched_table",
            "last_stats", "HqrError", "BatchedProblem", "BatchedGraph", "set_batched_launch",
-           "batched_launch"]
+           "batched_launch", "qz_batched"]

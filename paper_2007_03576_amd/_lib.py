@@ -28,7 +28,7 @@ EXPORTS = ["hqr_set_params", "hqr_get_params", "hqr_schur", "hqr_schur_ex", "hqr
            "hqr_eig_backward_batched", "hqr_last_stats", "hqr_finalize", "hqr_profile_enable",
            "hqr_profile_reset", "hqr_profile_read", "hqr_profile_ticks", "hqr_set_batched_launch",
            "hqr_get_batched_launch", "hqr_schur_batched_noalloc", "hqr_hessenberg",
-           "hqr_eigenvectors", "hqr_set_batched_table", "hqr_get_batched_table"]
+           "hqr_eigenvectors", "hqr_set_batched_table", "hqr_get_batched_table", "hqr_qz_batched"]
 
 
 class HqrError(RuntimeError):
@@ -53,6 +53,7 @@ def lib():
     L.hqr_eigenvectors.argtypes = [vp, vp, i64, i64, vp, vp, vp, i64, vp]
     L.hqr_schur_batched.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
     L.hqr_schur_batched_noalloc.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
+    L.hqr_qz_batched.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
     L.hqr_set_batched_launch.argtypes = [i32, i32]
     ip = ctypes.POINTER(ctypes.c_int32)
     L.hqr_set_batched_table.argtypes = [i32, ip, ip, ip]

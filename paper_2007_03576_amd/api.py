@@ -271,3 +271,54 @@ def eigvals(H: torch.Tensor) -> torch.Tensor:
     """Differentiable eigenvalues (defined in autograd.py)."""
     from .autograd import SchurEig
     return SchurEig.apply(H)
+
+
+def qz_batched(Hs: Sequence[torch.Tensor], Ts: Sequence[torch.Tensor], want_qz: bool = True, stream=None):
+    """QZ variant for small pairs: lists of square float64 GPU matrices (H_b
+    upper Hessenberg, T_b upper triangular, orders 0..64, one device).
+    Returns (S list, T list, Q list or None, Z list or None, alpha list
+    (complex), beta list, info tensor) with Q^T H Z = S, Q^T T Z = T' per pair
+    (hqr_qz_batched)."""
+    if len(Hs) != len(Ts):
+        raise ValueError("Hs and Ts differ in length")
+    for H, T in zip(Hs, Ts):
+        _require_device(H, "H")
+        _require_device(T, "T")
+        if H.shape != T.shape or H.dim() != 2 or H.shape[0] != H.shape[1]:
+            raise ValueError("each pair must be two square matrices of the same order")
+    if not Hs:
+        return [], [], [], [], [], [], torch.zeros(0, dtype=torch.int32)
+    dev = Hs[0].device
+    sizes = [int(H.shape[0]) for H in Hs]
+    offs, eoffs = [0], [0]
+    for n in sizes[:-1]:
+        offs.append(offs[-1] + n * n)
+        eoffs.append(eoffs[-1] + n)
+    Hp, Tp = pack(Hs), pack(Ts)
+    Qp = Zp = None
+    if want_qz:
+        Qp = torch.cat([torch.eye(n, dtype=torch.float64, device=dev).reshape(-1) for n in sizes])
+        Zp = Qp.clone()
+    tot = max(sum(sizes), 1)
+    ar = torch.zeros(tot, dtype=torch.float64, device=dev)
+    ai = torch.zeros_like(ar)
+    be = torch.zeros_like(ar)
+    info = torch.zeros(len(sizes), dtype=torch.int32, device=dev)
+    d_off = torch.tensor(offs, dtype=torch.int64, device=dev)
+    d_n = torch.tensor(sizes, dtype=torch.int32, device=dev)
+    d_eo = torch.tensor(eoffs, dtype=torch.int64, device=dev)
+    P = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    rc = lib().hqr_qz_batched(P(Hp), P(Tp), P(Qp), P(Zp), P(d_off), P(d_n), len(sizes), P(ar), P(ai), P(be),
+                              P(d_eo), P(info), _stream_handle(stream))
+    check(rc, "hqr_qz_batched")
+    S, Tt, Q, Z, alpha, beta = [], [], [], [], [], []
+    for b, n in enumerate(sizes):
+        o, e = offs[b], eoffs[b]
+        S.append(Hp[o:o + n * n].reshape(n, n).t())
+        Tt.append(Tp[o:o + n * n].reshape(n, n).t())
+        if want_qz:
+            Q.append(Qp[o:o + n * n].reshape(n, n).t())
+            Z.append(Zp[o:o + n * n].reshape(n, n).t())
+        alpha.append(torch.complex(ar[e:e + n], ai[e:e + n]))
+        beta.append(be[e:e + n])
+    return S, Tt, (Q if want_qz else None), (Z if want_qz else None), alpha, beta, info

@@ -193,6 +193,10 @@ hipError_t launch_seq_aed(double *T, int w, double *V, double s, Defl dfl, int n
                           hipStream_t strm);
 hipError_t launch_updates(const UpdBatch &b, hipStream_t s);
 void free_update_ws();
+// QZ variant: one workgroup per Hessenberg-triangular pair of order <= 64 (hqr_qz.hip).
+hipError_t launch_qz_batched(double *H, double *T, double *Q, double *Z, const int64_t *offsets, const int32_t *n,
+                             int batch, double *alphar, double *alphai, double *beta, const int64_t *eoff,
+                             int32_t *info, hipStream_t s);
 // C = beta C + alpha op(A) op(B) (column major; op 1 = transposed), FP64 MFMA,
 // 64 x 64 tiles; tag 0 / 1 only selects the kernel name shown in profiles.
 hipError_t gemm_mfma(int tag, int mm, int nn, int kk, double alpha, const double *A, int64_t lda, int opA,

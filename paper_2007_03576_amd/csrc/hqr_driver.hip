@@ -1327,6 +1327,26 @@ int hqr_finalize(void)
     return 0;
 }
 
+int hqr_qz_batched(double *H, double *T, double *Q, double *Z, const int64_t *offsets, const int32_t *n,
+                   int32_t batch, double *alphar, double *alphai, double *beta, const int64_t *eig_offsets,
+                   int32_t *info, void *stream)
+{
+    if (batch < 0) return -7;
+    if (batch == 0) return 0;
+    if (!H) return -1;
+    if (!T) return -2;
+    if (!offsets) return -5;
+    if (!n) return -6;
+    if (!alphar) return -8;
+    if (!alphai) return -9;
+    if (!beta) return -10;
+    if (!eig_offsets) return -11;
+    if (!info) return -12;
+    CK(launch_qz_batched(H, T, Q, Z, offsets, n, batch, alphar, alphai, beta, eig_offsets, info,
+                         (hipStream_t)stream));
+    return 0;
+}
+
 int hqr_schur_batched(double *H, double *Q, const int64_t *offsets, const int32_t *n, int32_t batch, double *wr,
                       double *wi, const int64_t *eig_offsets, int32_t *info, void *stream)
 {
