@@ -297,8 +297,8 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=2048)
     ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--small-shifts", type=int, default=0)
-    ap.add_argument("--extra-only", action="store_true",
-                    help="only the batched and differentiation lines (for profiling those kernels)")
+    ap.add_argument("--extra-only", nargs="?", const="all", default=None, choices=["all", "batched", "grad"],
+                    help="only the batched and/or differentiation lines (for profiling those kernels)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run 5 plain device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -317,7 +317,12 @@ def main():
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if args.extra_only:
-        print(json.dumps({"batched": batched_run(args.seed), "grad": grad_run(args.seed)}))
+        out = {}
+        if args.extra_only in ("all", "batched"):
+            out["batched"] = batched_run(args.seed)
+        if args.extra_only in ("all", "grad"):
+            out["grad"] = grad_run(args.seed)
+        print(json.dumps(out))
         return
 
     import numpy as np

@@ -981,20 +981,20 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
             int want = P.ns;
             if (want > kbot - ktop - 1) want = (kbot - ktop - 1) & ~1;
             int cnt = std::min(want, kbot - ktop);
-            int lo_row = std::max(ktop, kbot - cnt - 2);
+            int lo_row = std::max(ktop, kbot - std::min(cnt + 2, MAXCAND - 1));
             int rows = kbot - lo_row + 1;
-            std::vector<double> diag(rows), sub(rows);
-            // fetch the needed diagonal and subdiagonal entries
-            for (int i = 0; i < rows; ++i) {
-                int r = lo_row + i;
-                CK(hipMemcpyAsync(&diag[i], V.H + r + (int64_t)r * V.ld, sizeof(double), hipMemcpyDeviceToHost,
-                                  C.hi));
-                if (r > 0)
-                    CK(hipMemcpyAsync(&sub[i], V.H + r + (int64_t)(r - 1) * V.ld, sizeof(double),
-                                      hipMemcpyDeviceToHost, C.hi));
-                else
-                    sub[i] = 0.0;
-            }
+            // the diagonal and subdiagonal entries of rows lo_row..kbot: both
+            // are vectors of stride ld + 1, fetched by one strided copy each
+            // into the pinned candidate arrays (their values were taken above)
+            double *diag = S.cr, *sub = S.ci;
+            const size_t pitch = (size_t)(V.ld + 1) * sizeof(double);
+            CK(hipMemcpy2DAsync(diag, sizeof(double), V.H + lo_row + (int64_t)lo_row * V.ld, pitch, sizeof(double),
+                                rows, hipMemcpyDeviceToHost, C.hi));
+            const int s0 = (lo_row == 0) ? 1 : 0; // row 0 has no subdiagonal entry
+            if (s0) sub[0] = 0.0;
+            if (rows > s0)
+                CK(hipMemcpy2DAsync(sub + s0, sizeof(double), V.H + (lo_row + s0) + (int64_t)(lo_row + s0 - 1) * V.ld,
+                                    pitch, sizeof(double), rows - s0, hipMemcpyDeviceToHost, C.hi));
             CK(hipStreamSynchronize(C.hi));
             for (int i = kbot; i >= ktop + 2 && nsh + 2 <= want; i -= 2) {
                 int li = i - lo_row;

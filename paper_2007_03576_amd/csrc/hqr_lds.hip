@@ -2923,7 +2923,7 @@ __device__ void bw_left(double *X, int64_t ldx, int cols, int nw, const double *
 // shifts once the active block is small (or after three AED steps without a
 // deflation).  Returns 0 or the failure code of the small solver / the
 // iteration limit (1-based row).
-__device__ int batched_aed_solve(SmemB &S, double *A, int n, double *Q, int nwb, int nsb, const Defl &dfl)
+__device__ __forceinline__ int batched_aed_solve(SmemB &S, double *A, int n, double *Q, int nwb, int nsb, const Defl &dfl)
 {
     const int nz = Q ? n : 0;
     double *Z = Q ? Q : A; // without Q: no Z rows (nz = 0)

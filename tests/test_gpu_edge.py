@@ -9,6 +9,8 @@ what the mathematics fixes for them:
 * an iteration limit too small to converge: info > 0, and the returned (T, Q)
   is still an orthogonal similarity of H (backward error and orthogonality
   within 100 n u), with the rows below info converged;
+* exceptional shifts forced every step or every other step (kexsh 1, 2):
+  still a valid Schur form with the oracle's eigenvalues;
 * the norm-stable and fixed deflation conditions (Sec. 5.6, items 2 and 3)
   against the oracle run under the same conditions;
 * the batched form with empty, 1x1 and 2x2 matrices among larger ones.
@@ -125,6 +127,25 @@ def test_iteration_limit(gpu, n, params):
         d = np.abs(w[info:, None] - wo[None, :]).min(axis=1)
         lam, kap = checks.eig_condition(H)
         assert d.max() <= 1e-10 * max(kap.max(), 1.0) * np.linalg.norm(H)
+
+
+@pytest.mark.parametrize("kexsh", [1, 2])
+@pytest.mark.parametrize("n,params", [(200, {"ns": 16, "nw": 48, "nmin": 12}), (500, {"ns": 32, "nw": 96})])
+def test_exceptional_shifts(gpu, kexsh, n, params):
+    p = dict(params)
+    p["kexsh"] = kexsh
+    _say(f"case exceptional shifts n={n} params={p}")
+    H = hi.hessrand(n, seed=31 + n)
+    T, Q, w, info = run_gpu(H, p)
+    assert info == 0
+    ok, msg = checks.structure_ok(T, w)
+    assert ok, msg
+    be, ob = checks.rel_backward(H, T, Q), checks.orth(Q)
+    _say(f"backward {be / U:.1f} u orth {ob / U:.1f} u")
+    assert be <= 100 * n * U and ob <= 100 * n * U
+    _, _, wo, oi, _ = oracle.schur(H, want_q=False)
+    assert oi == 0
+    eig_match_oracle(H, w, wo, f"kexsh{kexsh}")
 
 
 @pytest.mark.parametrize("mode", [1, 2])
