@@ -283,6 +283,28 @@ def cpu_baseline(spec, seed, target_n):
                       f"{os.cpu_count()} logical CPUs (the oracle is single-threaded C)"}
 
 
+def lapack_context(spec, seed, target_n):
+    """Context, not the oracle: the host's LAPACK real Schur driver (dgees
+    through scipy, OpenBLAS on all its threads) on the same bounded sample as
+    cpu_baseline.  dgees also runs the Hessenberg reduction and forms its
+    orthogonal factor (on an input that is already Hessenberg), so it does
+    more than the Schur phase alone."""
+    import scipy
+    import scipy.linalg as sl
+    import hqr_inputs as hi
+    from threadpoolctl import threadpool_info
+    if spec["gen"] != "gaussian":
+        return None
+    H = hi.gaussian_hessenberg(target_n, seed=seed)
+    t0 = time.perf_counter()
+    sl.schur(H, output="real")
+    dt = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+    return {"value": 10.0 * target_n ** 3 / dt / 1e12, "unit": "TFLOP/s (10n^3 nominal)", "threads": threads,
+            "kind": "LAPACK dgees (scipy %s, OpenBLAS)" % scipy.__version__,
+            "sample": f"one real Schur decomposition of the same generator's matrix at n={target_n}: {dt:.2f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +426,7 @@ def main():
             out["paper_scale"] = paper_scale_run(args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.seed, args.cpu_n)
+        out["lapack_context"] = lapack_context(spec, args.seed, args.cpu_n)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))

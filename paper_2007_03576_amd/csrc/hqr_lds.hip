@@ -38,6 +38,7 @@ struct ReorderState {
     int pos[2][MV], sz[MV], dst[MV]; // moves in flight (ring indexed by move id), position double buffered
     int sj[MV], sm[MV];              // exchange of each lane: first row and order (0: none)
     int roff[MV + 1], coff[MV + 1];  // prefix sums of the row and column work items per lane
+    int xj[MV], xk[MV], xr[MV];      // exchange of each lane: first row, kind, outcome
     int head, tail, ns, ilst, halt, chk_done, done, rtot, ctot;
 };
 
@@ -1584,17 +1585,24 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
     __syncthreads();
     int par = 0, nphase = 0;
     while (!R.done) {
+        // wave 0's scheduling state, carried across the exchange step
+        const int lane = tid;
+        int head = 0, tail = 0, nact = 0;
+        bool halt0 = false, chk_done = false;
+        int ns = 0, ilst = 0;
+        int slot = -1, pos = 0, sz = 0, dst = 0;
+        int sj = -1, sp = 0;
+        bool fin = false, bad = false, created = false;
         if (tid < 64) {
-            const int lane = tid;
             // (a) scheduling from the state left by the previous phase; no LDS
             // writes until every lane has read what it needs
-            const int head = R.head, tail = R.tail, nact = tail - head;
-            const bool halt0 = R.halt != 0;
-            bool chk_done = R.chk_done != 0;
-            int ns = R.ns, ilst = R.ilst;
-            int slot = -1, pos = 0, sz = 0, dst = 0;
-            int sj = -1, sp = 0;
-            bool fin = false, bad = false, created = false;
+            head = R.head;
+            tail = R.tail;
+            nact = tail - head;
+            halt0 = R.halt != 0;
+            chk_done = R.chk_done != 0;
+            ns = R.ns;
+            ilst = R.ilst;
             if (!halt0 && lane < nact) {
                 const int id = head + lane;
                 slot = id % MV;
@@ -1672,16 +1680,29 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
                     break;
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            // (b) the exchanges: each swapping lane forms its transformation,
-            // writes the new diagonal block into T and G into its slot
-            bool ok = true, split = false;
-            if (sj >= 0) {
-                double *G = R.G + lane * 16;
-                if (sp == 1 && sz == 1) {
-                    const double t11 = T[sj + sj * ldt], t12 = T[sj + (sj + 1) * ldt];
-                    const double t22 = T[(sj + 1) + (sj + 1) * ldt];
+            // publish the lane's exchange: kind 0 (1x1 past 1x1), 1 (1x1
+            // past 2x2), 2 (2x2 past 1x1) or 3 (2x2 past 2x2)
+            if (lane < MV) {
+                R.xj[lane] = sj;
+                R.xk[lane] = (sj >= 0) ? 2 * (sz - 1) + (sp - 1) : -1;
+            }
+        }
+        __syncthreads();
+        // (b) the exchanges: wave w forms those of kind w (the kinds run on
+        // different SIMDs instead of one after another in divergent lanes of
+        // one wave), writes the new diagonal block into T, G into the lane's
+        // slot and the outcome (1 done, 2 done with a 2x2 block split, 0
+        // rejected) into xr
+        {
+            const int w = tid >> 6, l = tid & 63;
+            if (l < MV && R.xk[l] == w) {
+                const int j = R.xj[l];
+                double *G = R.G + l * 16;
+                bool ok = true;
+                int szl = 1;
+                if (w == 0) {
+                    const double t11 = T[j + j * ldt], t12 = T[j + (j + 1) * ldt];
+                    const double t22 = T[(j + 1) + (j + 1) * ldt];
                     const double rr = hypot(t12, t22 - t11);
                     double cs = 1.0, sn = 0.0;
                     if (rr != 0.0) {
@@ -1692,19 +1713,26 @@ __device__ __forceinline__ int aed_deflate(SmemCore &S, double *T, int ldt, int 
                     G[1] = sn;
                     G[2] = -sn;
                     G[3] = cs;
-                    T[sj + sj * ldt] = t22;
-                    T[sj + (sj + 1) * ldt] = cs * (-t11 * sn + t12 * cs) + sn * (t22 * cs);
-                    T[(sj + 1) + sj * ldt] = 0.0;
-                    T[(sj + 1) + (sj + 1) * ldt] = t11;
-                } else if (sp == 1) {
-                    ok = swap_xform<1, 2>(T, ldt, sj, smlnum, G);
-                } else if (sz == 1) {
-                    ok = swap_xform<2, 1>(T, ldt, sj, smlnum, G);
+                    T[j + j * ldt] = t22;
+                    T[j + (j + 1) * ldt] = cs * (-t11 * sn + t12 * cs) + sn * (t22 * cs);
+                    T[(j + 1) + j * ldt] = 0.0;
+                    T[(j + 1) + (j + 1) * ldt] = t11;
+                } else if (w == 1) {
+                    ok = swap_xform<2, 1>(T, ldt, j, smlnum, G);
+                } else if (w == 2) {
+                    ok = swap_xform<1, 2>(T, ldt, j, smlnum, G);
+                    szl = 2;
                 } else {
-                    ok = swap_xform<2, 2>(T, ldt, sj, smlnum, G);
+                    ok = swap_xform<2, 2>(T, ldt, j, smlnum, G);
+                    szl = 2;
                 }
-                if (ok && sz == 2 && T[(sj + 1) + sj * ldt] == 0.0) split = true;
+                R.xr[l] = !ok ? 0 : ((szl == 2 && T[(j + 1) + j * ldt] == 0.0) ? 2 : 1);
             }
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int res = (sj >= 0) ? R.xr[lane] : 1;
+            const bool ok = res != 0, split = res == 2;
             const bool moved = (sj >= 0) && ok;
             if (slot >= 0) {
                 R.pos[par ^ 1][slot] = moved ? sj : pos;
