@@ -229,7 +229,7 @@ int hqr_eig_backward_batched(const double *T, const double *Q, const int64_t *of
 
 /* Generalized real Schur form of many small Hessenberg-triangular pairs (the
  * QZ variant: Sec. 2, remarks on the generalized case; Sec. 3.2 'push
- * infinities').  Pair b has order n[b] (0..64), H_b upper Hessenberg and T_b
+ * infinities').  Pair b has order n[b] >= 0, H_b upper Hessenberg and T_b
  * upper triangular (entries below are ignored), each stored column major
  * with leading dimension n[b] at H + offsets[b] and T + offsets[b] (device).
  * Out: H_b = S_b = Q_b^T H_b Z_b quasi upper triangular (2x2 blocks only for
@@ -240,10 +240,13 @@ int hqr_eig_backward_batched(const double *T, const double *Q, const int64_t *of
  * order at eig_offsets[b] (beta >= 0; beta = 0 marks an infinite eigenvalue,
  * decided by |t_kk| <= u ||T_b||_F as in the paper; such an eigenvalue is
  * chased to the top of its block by rotations and deflated there).  Double
- * implicit shift QZ, one workgroup per pair held in LDS.  info[b] = 0, k > 0
- * when the iteration limit 30 max(10, n) was reached with row k-1 unconverged,
- * -1 for an order outside 0..64.  Asynchronous on `stream`.  Returns 0, -k
- * for a bad argument k (NULL pointer, batch < 0), or -1000-e for a HIP error. */
+ * implicit shift QZ, one workgroup per pair: pairs of order <= 64 are held in
+ * LDS with Q and Z, larger ones are reduced in place in global memory (below
+ * the subdiagonal of H and the diagonal of T the arrays are overwritten with
+ * zeros).  info[b] = 0, k > 0 when the iteration limit 30 max(10, n) was
+ * reached with row k-1 unconverged, -1 for a negative order.  Asynchronous on
+ * `stream`.  Returns 0, -k for a bad argument k (NULL pointer, batch < 0), or
+ * -1000-e for a HIP error. */
 int hqr_qz_batched(double *H, double *T, double *Q, double *Z, const int64_t *offsets, const int32_t *n,
                    int32_t batch, double *alphar, double *alphai, double *beta, const int64_t *eig_offsets,
                    int32_t *info, void *stream);

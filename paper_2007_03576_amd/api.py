@@ -274,8 +274,9 @@ def eigvals(H: torch.Tensor) -> torch.Tensor:
 
 
 def qz_batched(Hs: Sequence[torch.Tensor], Ts: Sequence[torch.Tensor], want_qz: bool = True, stream=None):
-    """QZ variant for small pairs: lists of square float64 GPU matrices (H_b
-    upper Hessenberg, T_b upper triangular, orders 0..64, one device).
+    """QZ variant for batches of pairs: lists of square float64 GPU matrices
+    (H_b upper Hessenberg, T_b upper triangular, one device; orders up to 64
+    are reduced in LDS, larger ones in global memory).
     Returns (S list, T list, Q list or None, Z list or None, alpha list
     (complex), beta list, info tensor) with Q^T H Z = S, Q^T T Z = T' per pair
     (hqr_qz_batched)."""

@@ -1,6 +1,7 @@
 """QZ variant on the GPU (hqr_qz_batched) against the oracle's QZ: pairs of
-orders 1..64 in one batch, some with exact zeros on T's diagonal (infinite
-eigenvalues), all with T and Q, Z.  Compared on what a generalized Schur form
+orders 1..64 (held in LDS) and 65..200 (reduced in global memory) in one
+batch, some with exact zeros on T's diagonal (infinite eigenvalues), all with
+T and Q, Z.  Compared on what a generalized Schur form
 fixes: the finite eigenvalues (matched, within 1e-9 of the larger magnitude),
 the number of infinite eigenvalues, backward errors of both factors and
 orthogonality of Q and Z within 100 n u, exact structure (S quasi
@@ -103,15 +104,57 @@ def test_qz_batched_infinite_eigenvalues(gpu):
 
 
 def test_qz_identity_T_and_rejections(gpu):
+    import ctypes
     import torch
-    import paper_2007_03576_amd as hq
-    _say("case QZ with T = I, and an order above 64")
+    from paper_2007_03576_amd._lib import lib
+    _say("case QZ with T = I, and a negative order through the C-ABI")
     H, _ = pencil(40, 77)
     S, Tt, Q, Z, alpha, beta, info = run([(H, np.eye(40))])
     assert info[0] == 0
     lam = alpha[0] / beta[0]
     assert match(lam, np.linalg.eigvals(H)) <= 1e-10 * max(1.0, np.abs(lam).max())
-    big = torch.zeros(65, 65, dtype=torch.float64, device="cuda")
-    out = hq.qz_batched([big], [big.clone()])
+    d = torch.zeros(16, dtype=torch.float64, device="cuda")
+    offs = torch.zeros(2, dtype=torch.int64, device="cuda")
+    nn = torch.tensor([-1, 0], dtype=torch.int32, device="cuda")
+    info = torch.full((2,), 7, dtype=torch.int32, device="cuda")
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    rc = lib().hqr_qz_batched(P(d), P(d), None, None, P(offs), P(nn), 2, P(d), P(d), P(d), P(offs), P(info), None)
     torch.cuda.synchronize()
-    assert int(out[-1][0]) == -1
+    assert rc == 0
+    assert info.cpu().tolist() == [-1, 0]
+
+
+def test_qz_global_memory_orders(gpu):
+    sizes = [65, 80, 100, 128, 150, 200, 3, 64]
+    nzero = [0, 2, 0, 1, 0, 3, 0, 1]
+    _say(f"case QZ orders above the LDS limit {sizes}")
+    pairs = [pencil(n, 2600 + i, nz) for i, (n, nz) in enumerate(zip(sizes, nzero))]
+    S, Tt, Q, Z, alpha, beta, info = run(pairs)
+    assert np.all(info == 0), info
+    for i, (H, T) in enumerate(pairs):
+        check_pair(H, T, S[i], Tt[i], Q[i], Z[i], alpha[i], beta[i], f"global{i}_n{sizes[i]}")
+        if nzero[i]:
+            assert int((beta[i] == 0).sum()) >= 1
+
+
+def test_qz_global_memory_without_factors(gpu):
+    import torch
+    import paper_2007_03576_amd as hq
+    sizes = [90, 33, 140]
+    _say(f"case QZ without Q and Z {sizes}")
+    pairs = [pencil(n, 3100 + i, 1) for i, n in enumerate(sizes)]
+    Hs = [torch.from_numpy(np.ascontiguousarray(H)).cuda() for H, _ in pairs]
+    Ts = [torch.from_numpy(np.ascontiguousarray(T)).cuda() for _, T in pairs]
+    S, Tt, Q, Z, alpha, beta, info = hq.qz_batched(Hs, Ts, want_qz=False)
+    torch.cuda.synchronize()
+    assert Q is None and Z is None
+    assert np.all(info.cpu().numpy() == 0)
+    for i, (H, T) in enumerate(pairs):
+        a, b = alpha[i].cpu().numpy(), beta[i].cpu().numpy()
+        assert np.all(np.tril(Tt[i].cpu().numpy(), -1) == 0.0)
+        assert np.all(np.tril(S[i].cpu().numpy(), -2) == 0.0)
+        _, _, _, _, ao, bo, oi = oracle.qz(H, T, want_qz=False)
+        assert oi == 0
+        assert int((b == 0).sum()) == int((bo == 0).sum())
+        lam, lo = a[b > 0] / b[b > 0], ao[bo > 0] / bo[bo > 0]
+        assert match(lam, lo) <= 1e-9 * max(1.0, float(np.abs(lo).max()))
