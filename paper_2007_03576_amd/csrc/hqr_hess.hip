@@ -249,6 +249,162 @@ __global__ void __launch_bounds__(HT) k_hh_col(double *A, int64_t lda, int m, in
     if (tid == 0) tau[j] = tj;
 }
 
+// k_hh_col for m <= 2 HT: each thread owns rows tid and tid + HT and keeps
+// their entries of the column in registers from its first load to the final
+// reflector (no store and reload of the work column between the steps), loads
+// its rows of V(:, :j) once for the update and the w_j product, and receives
+// x(c+1) through LDS.  Every kernel starts with a cold L2 (the GEMV before it
+// ran on all XCDs), so each avoided global round trip is a memory latency.
+__global__ void __launch_bounds__(HT) k_hh_col2(double *A, int64_t lda, int m, int k, int j, int form,
+                                                double *V, double *Y, double *Tm, double *W, double *tau,
+                                                const double *part, int nchunk)
+{
+    __shared__ double red[16 * NBH];
+    __shared__ double sv[NBH];
+    __shared__ double sv2[NBH];
+    __shared__ double sT[NBH * NBH];
+    __shared__ double sx0;
+    const int tid = threadIdx.x;
+    const int64_t ldm = m;
+    const int c = k + j;
+    // the loads that do not depend on the step below go out first
+    if (form) {
+        if (tid < j) sv[tid] = V[c + tid * ldm];
+        for (int it = tid; it < NBH * j; it += HT) sT[it] = Tm[it];
+    }
+    if (j > 0) {
+        const int jp = j - 1;
+        const double tp = tau[jp];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int r = tid + q * HT;
+            if (r >= m) continue;
+            double y0 = 0.0, y1 = 0.0;
+#pragma unroll 8
+            for (int qq = 0; qq < nchunk; qq += 2) {
+                y0 += part[(int64_t)qq * m + r];
+                if (qq + 1 < nchunk) y1 += part[(int64_t)(qq + 1) * m + r];
+            }
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < NBH; ++i)
+                if (i < jp) s += Y[r + i * ldm] * W[i + jp * NBH];
+            Y[r + jp * ldm] = tp * ((y0 + y1) - s);
+        }
+    }
+    if (!form) return;
+    __syncthreads();
+    // x = A0(:, c) - Y(:, :j) V(c, :j)^T, and the partial sums of V^T x
+    double xr[2] = {0.0, 0.0};
+    double loc[NBH];
+#pragma unroll
+    for (int i = 0; i < NBH; ++i) loc[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = tid + q * HT;
+        if (r >= m) continue;
+        double v = A[r + (int64_t)c * lda];
+#pragma unroll
+        for (int i = 0; i < NBH; ++i)
+            if (i < j) v -= Y[r + i * ldm] * sv[i];
+        xr[q] = v;
+        if (r >= k + 1) {
+#pragma unroll
+            for (int i = 0; i < NBH; ++i)
+                if (i < j) loc[i] += V[r + i * ldm] * v;
+        }
+    }
+    // x(k+1:) <- Q_{j-1}^T x = x - V T^T (V^T x)
+    hh_multi_sum(loc, j, red, sv);
+    if (tid < j) {
+        double t = 0.0;
+        for (int l = 0; l <= tid; ++l) t += sT[l + tid * NBH] * sv[l];
+        sv2[tid] = t;
+    }
+    __syncthreads();
+    double vr[2][NBH]; // this thread's rows of V(:, :j), kept for the w_j product
+    double amax = 0.0, ssr = 0.0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = tid + q * HT;
+#pragma unroll
+        for (int i = 0; i < NBH; ++i) vr[q][i] = 0.0;
+        if (r >= m) continue;
+        double v = xr[q];
+        if (r >= k + 1) {
+#pragma unroll
+            for (int i = 0; i < NBH; ++i)
+                if (i < j) {
+                    vr[q][i] = V[r + i * ldm];
+                    v -= vr[q][i] * sv2[i];
+                }
+        }
+        xr[q] = v;
+        if (r <= c) A[r + (int64_t)c * lda] = v; // final rows 0..c of column c
+        if (r == c + 1) sx0 = v;
+        if (r >= c + 2) {
+            amax = fmax(amax, fabs(v));
+            ssr = fma(v, v, ssr);
+        }
+    }
+    hh_max_sum(amax, ssr, red); // its barriers also publish sx0
+    const double x0 = sx0;
+    double tnorm = 0.0;
+    if (amax >= 0x1p-480 && amax <= 0x1p+480) {
+        tnorm = sqrt(ssr);
+    } else if (amax > 0.0) {
+        double ss = 0.0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int r = tid + q * HT;
+            if (r >= c + 2 && r < m) {
+                const double t = xr[q] / amax;
+                ss += t * t;
+            }
+        }
+        ss = hh_sum(ss, red);
+        tnorm = amax * sqrt(ss);
+    }
+    double tj = 0.0, beta = x0, scal = 0.0;
+    if (amax > 0.0) {
+        const double nrm = hypot(x0, tnorm);
+        beta = (x0 >= 0.0) ? -nrm : nrm;
+        tj = (beta - x0) / beta;
+        scal = 1.0 / (x0 - beta);
+    }
+    // v_j (unit at c+1, zero above) into V(:, j), the reduced column, w_j = V(:, :j)^T v_j
+#pragma unroll
+    for (int i = 0; i < NBH; ++i) loc[i] = 0.0;
+    double *x = V + (int64_t)j * ldm;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = tid + q * HT;
+        if (r >= m) continue;
+        double v;
+        if (r <= c) v = 0.0;
+        else if (r == c + 1) v = 1.0;
+        else v = (tj != 0.0) ? xr[q] * scal : 0.0;
+        x[r] = v;
+        if (r == c + 1) A[r + (int64_t)c * lda] = beta;
+        else if (r > c + 1) A[r + (int64_t)c * lda] = 0.0;
+        if (r >= c + 1) {
+#pragma unroll
+            for (int i = 0; i < NBH; ++i)
+                if (i < j) loc[i] += vr[q][i] * v;
+        }
+    }
+    hh_multi_sum(loc, j, red, sv);
+    if (tid < j) { // T(:j, j) = -tau_j T(:j, :j) w_j, one thread per row
+        W[tid + j * NBH] = sv[tid];
+        double t = 0.0;
+        for (int l = tid; l < j; ++l) t += sT[tid + l * NBH] * sv[l];
+        Tm[tid + j * NBH] = -tj * t;
+    } else if (tid < NBH) {
+        Tm[tid + j * NBH] = (tid == j) ? tj : 0.0;
+    }
+    if (tid == 0) tau[j] = tj;
+}
+
 // Partial sums of y = A(:, c+1:m) v(c+1:m) for column chunks: grid (row
 // blocks of 256, nchunk); part[q * m + r].
 __global__ void __launch_bounds__(256) k_hh_gemv(const double *A, int64_t lda, int m, int c, const double *v,
@@ -361,17 +517,18 @@ hipError_t hess_reduce(double *A, int64_t lda, int m, int nr, double *Z, int64_t
     for (int k = 0; k < m - 2; k += NBH) {
         const int nb = std::min(NBH, m - 2 - k);
         int nchunk = 1;
+        // columns of at most 2 HT rows: the register-resident column kernel
+        auto col = (m <= 2 * HT) ? k_hh_col2 : k_hh_col;
         for (int j = 0; j < nb; ++j) {
             const int c = k + j;
-            hipLaunchKernelGGL(k_hh_col, dim3(1), dim3(HT), 0, s, A, lda, m, k, j, 1, V, Y, Tm, W, tau, part,
-                               nchunk);
+            hipLaunchKernelGGL(col, dim3(1), dim3(HT), 0, s, A, lda, m, k, j, 1, V, Y, Tm, W, tau, part, nchunk);
             const int ncol = m - (c + 1);
             nchunk = std::max(1, std::min(nchunk_max, std::min(ncol / 16, (1024 + rblk - 1) / rblk)));
             hipLaunchKernelGGL(k_hh_gemv, dim3(rblk, nchunk), dim3(256), 0, s, A, lda, m, c, V + (size_t)j * mm,
                                part, nchunk);
         }
         // complete Y(:, nb-1)
-        hipLaunchKernelGGL(k_hh_col, dim3(1), dim3(HT), 0, s, A, lda, m, k, nb, 0, V, Y, Tm, W, tau, part, nchunk);
+        hipLaunchKernelGGL(col, dim3(1), dim3(HT), 0, s, A, lda, m, k, nb, 0, V, Y, Tm, W, tau, part, nchunk);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int c1 = k + nb; // first column right of the panel
         const int r0 = k + 1;  // first row the reflectors touch
