@@ -37,7 +37,8 @@ extern "C" {
  *   ns      shifts per sweep (even)                         (Sec. 2.3)
  *   nw      AED window size, at most 1024                    (Sec. 2.5)
  *   nmin    blocks of order <= nmin go to the small solver   (task 'small Schur', Sec. 3.2)
- *   nibble  skip the sweep when 100*nd > nibble*nw           (Sec. 2.5, repeated AED)
+ *   nibble  skip the sweep when 100*nd > nibble*nw           (Sec. 2.5, repeated AED;
+ *           0 = 60 for active blocks above 256 rows, 14 for smaller ones) 
  *   kexsh   exceptional shifts after kexsh steps without deflation
  *   itmax   iteration limit (AED steps + sweeps)             (Sec. 2.1)
  *   window  bulge-chasing window order (<= 96)              (Sec. 3.2, 'push bulges')
@@ -68,7 +69,9 @@ extern "C" {
  *              below the predicted time of the update work still queued on
  *              the deferred stream, which it would overlap; windows above
  *              aed_seq_max always run in parallel.  Other values are rejected.
- *   aed_seq_max  largest window the sequential AED takes (0 = 512; at most 1024) */
+ *   aed_seq_max  largest window the sequential AED takes (0 = 512; at most 1024)
+ *   aed_nibble   nibble of the recursive solve of AED windows larger than 96
+ *              (0 = automatic) */
 typedef struct hqr_params {
     int ns, nw, nmin, nibble, kexsh;
     int64_t itmax;
@@ -79,6 +82,7 @@ typedef struct hqr_params {
     int small_shifts;
     int aed_ns, aed_nw, aed_nmin;
     int aed_mode, aed_seq_max;
+    int aed_nibble;
 } hqr_params;
 
 /* Process-wide defaults used by later calls.  Returns 0 or -1 (NULL / invalid). */

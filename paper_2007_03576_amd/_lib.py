@@ -21,7 +21,7 @@ class HqrParams(ctypes.Structure):
                 ("defl_mode", ctypes.c_int), ("defl_thold", ctypes.c_double),
                 ("streams", ctypes.c_int), ("small_shifts", ctypes.c_int),
                 ("aed_ns", ctypes.c_int), ("aed_nw", ctypes.c_int), ("aed_nmin", ctypes.c_int),
-                ("aed_mode", ctypes.c_int), ("aed_seq_max", ctypes.c_int)]
+                ("aed_mode", ctypes.c_int), ("aed_seq_max", ctypes.c_int), ("aed_nibble", ctypes.c_int)]
 
 
 EXPORTS = ["hqr_set_params", "hqr_get_params", "hqr_schur", "hqr_schur_ex", "hqr_schur_batched",

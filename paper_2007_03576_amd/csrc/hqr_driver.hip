@@ -83,7 +83,26 @@ struct Params {
     double defl_thold;            // threshold of the fixed conditions
     int aed_mode;                 // large AED windows: 0 adaptive, 1 sequential, 2 parallel (Sec. 3.5)
     int seq_max;                  // largest window of the sequential AED
+    int aed_nibble;               // nibble of the recursive solve (0 = automatic)
 };
+
+// Reading of the repeated-AED heuristic (Sec. 2.5) on this GPU: the sweep is
+// skipped when an AED step deflated more than nibble % of its window.  An AED
+// step is a chain of one-CU kernels while a sweep over a large block spreads
+// over many CUs, so above NIBBLE_BIG_BLOCK rows the sweep is skipped only
+// after a very productive AED (measured at n = 16384, prescribed spectrum:
+// 14 % -> 23.7 s, 60 % -> 10.9 s, 100 % -> 10.8 s; at n = 4096, Gaussian,
+// where AED deflates about 85 % of each window, 14 % and 40 % alike); for
+// smaller blocks, where a sweep is a few small chase launches, LAPACK's 14 %
+// (the recursive solve of 256-windows at n = 4096: 14 % 0.68 s, 25 % 0.77 s,
+// 40 % 1.03 s).  An explicit nibble applies at every size.
+constexpr int NIBBLE_SMALL = 14, NIBBLE_BIG = 60, NIBBLE_BIG_BLOCK = 256;
+
+int nibble_for(const Params &P, int nh)
+{
+    if (P.nibble > 0) return P.nibble;
+    return nh > NIBBLE_BIG_BLOCK ? NIBBLE_BIG : NIBBLE_SMALL;
+}
 
 // Reading of automatic parameters: LAPACK's documented shift-count table and
 // an AED window of ns (order <= 500) or 3ns/2 above, capped where noted.
@@ -716,6 +735,7 @@ int big_aed(Ctx &C, const View &V, int ktop, int kbot, int w, int depth, int &nd
         if (C.P.aed_nw > 0) Pi.nw = C.P.aed_nw;
         if (C.P.aed_ns > 0) Pi.ns = C.P.aed_ns;
         if (C.P.aed_nmin > 0) Pi.nmin = C.P.aed_nmin;
+        if (C.P.aed_nibble > 0) Pi.nibble = C.P.aed_nibble;
         Pi.ns = std::min(Pi.ns, std::max(2, (w / 4) & ~1));
         Pi.itmax = C.P.itmax;
         View Vi{T, w, w, Vw, w, w};
@@ -971,9 +991,10 @@ int run(Ctx &C, const View &V, int ilo, int ihi, const Params &P, int depth, int
         if (depth == 0) progress_line(ilo, kbot - nd, nd);
         cr.assign(S.cr, S.cr + ncand);
         ci.assign(S.ci, S.ci + ncand);
+        const int nh_aed = kbot - ktop + 1; // the active block the AED step saw
         kbot -= nd;
         ndfl = (nd > 0) ? 1 : ndfl + 1;
-        if (nd > 0 && 100 * nd > P.nibble * wwin) continue;
+        if (nd > 0 && 100 * nd > nibble_for(P, nh_aed) * wwin) continue;
         if (kbot - ktop + 1 <= P.nmin) continue;
         int nsh = 0;
         if (ndfl % P.kexsh == 0) {
@@ -1076,7 +1097,7 @@ Params resolve(const hqr_params *pp, int n)
     if (P.ns < 2) P.ns = 2;
     P.nmin = p.nmin > 0 ? p.nmin : 75;
     P.nmin = std::max(12, std::min(P.nmin, MMAX));
-    P.nibble = p.nibble > 0 ? p.nibble : 14;
+    P.nibble = p.nibble > 0 ? p.nibble : 0; // 0: nibble_for's size rule
     P.kexsh = p.kexsh > 0 ? p.kexsh : 6;
     P.itmax = p.itmax > 0 ? p.itmax : 30 * (int64_t)std::max(10, n);
     P.window = p.window > 0 ? std::min(p.window, WMAX) : WMAX;
@@ -1092,6 +1113,7 @@ Params resolve(const hqr_params *pp, int n)
     P.defl_thold = p.defl_thold;
     P.aed_mode = p.aed_mode;
     P.seq_max = p.aed_seq_max > 0 ? std::min(p.aed_seq_max, MAX_UPDATE_K) : 512;
+    P.aed_nibble = p.aed_nibble > 0 ? p.aed_nibble : 0;
     return P;
 }
 
