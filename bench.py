@@ -1,10 +1,13 @@
 """Benchmark: Hessenberg -> real Schur form (multishift QR + AED) on one MI355X.
 
 One step = one full hqr_schur call (T and Q) on the benchmark matrix, with the
-input already resident in HBM.  The default workload is the n = 4096 Gaussian
-Hessenberg matrix (upper triangle and subdiagonal i.i.d. N(0,1), seed 2020)
-with 64 shifts per sweep and an AED window of 256, Q accumulated from I.
-Prints one JSON line (see the design doc for the fields).
+input already resident in HBM.  The default workload is the paper-scale
+configuration: n = 16384 with a prescribed spectrum (8192 real eigenvalues
+and 4096 conjugate pairs, Haar orthogonal similarity reduced to Hessenberg
+form on the GPU, seed 2020), 256 shifts per sweep and an AED window of 1024,
+Q accumulated from I.  The n = 4096 Gaussian Hessenberg configuration (64
+shifts, window 256), the batched and the differentiated forms are reported
+beside it.  Prints one JSON line (see the design doc for the fields).
 """
 import argparse
 import json
@@ -24,31 +27,46 @@ WORKLOADS = {
 }
 
 
-def make_input(spec, seed, dev):
-    """Device tensor holding H column-major (row-major storage of H^T)."""
+def make_input(spec, seed, dev, cache=None, name=""):
+    """(device tensor holding H column-major (row-major storage of H^T), the
+    prescribed eigenvalues or None).  With a cache directory the input is
+    read from there when present, else generated and written there (so that
+    a profiled run need not execute the generator's library kernels)."""
     import numpy as np
     import torch
     import hqr_inputs as hi
     n = spec["n"]
+    if cache:
+        path = os.path.join(cache, f"{name}_{seed}.npz")
+        if os.path.exists(path):
+            z = np.load(path)
+            ev = z["ev"] if z["ev"].size else None
+            return torch.from_numpy(z["Ht"]).to(dev), ev
+        Ht, ev = make_input(spec, seed, dev)
+        os.makedirs(cache, exist_ok=True)
+        np.savez(path, Ht=Ht.cpu().numpy(), ev=np.zeros(0) if ev is None else np.asarray(ev))
+        return Ht, ev
     if spec["gen"] == "prescribed" and n > 4096:
-        H, _ = hi.prescribed_hessenberg_device(n, seed=seed, device=dev)  # host reduction would take minutes
-        return H.t().contiguous()
+        H, ev = hi.prescribed_hessenberg_device(n, seed=seed, device=dev)  # host reduction would take minutes
+        return H.t().contiguous(), ev
+    ev = None
     if spec["gen"] == "gaussian":
         H = hi.gaussian_hessenberg(n, seed=seed)
     elif spec["gen"] == "hessrand":
         H = hi.hessrand(n, seed=seed)
     else:
-        H, _ = hi.prescribed_hessenberg(n, seed=seed)
-    return torch.from_numpy(np.ascontiguousarray(H.T)).to(dev)
+        H, ev = hi.prescribed_hessenberg(n, seed=seed)
+    return torch.from_numpy(np.ascontiguousarray(H.T)).to(dev), ev
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload="gaussian_hessenberg_n4096"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
-    (FETCH_SIZE and WRITE_SIZE, calibrated with a plain copy), or None when the
-    HIP sources changed since the counters were taken."""
+    of the workload (FETCH_SIZE and WRITE_SIZE, calibrated with a plain copy),
+    or None when there is none or the HIP sources changed since the counters
+    were taken."""
     import glob
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_iter_gaussian_hessenberg_n4096.md")
+    path = os.path.join(ROOT, "profiles", f"k_iter_{workload}.md")
     if not os.path.exists(path):
         return None
     rec = None
@@ -205,85 +223,102 @@ def grad_run(seed):
             "speedup_vs_plain": (512 / (fw + bw)) / plain_rate}
 
 
-def paper_scale_run(seed):
-    """The paper-scale configuration: one solve of the n = 16384 Hessenberg
-    matrix with a prescribed spectrum (8192 real eigenvalues, 4096 conjugate
-    pairs; Haar orthogonal similarity reduced to Hessenberg form on the GPU),
-    256 shifts per sweep, AED window 1024, Q accumulated, input resident in
-    HBM before the timed call.  Reports the seconds, the nominal 10 n^3
-    TFLOP/s, the accuracy (backward error, orthogonality, distance of every
-    computed eigenvalue to the prescribed spectrum and back), the kernel-class
+def solve_line(workload, seed, steps, warmup, streams=2, small_shifts=0, cache=None):
+    """`warmup` untimed and `steps` timed hqr_schur calls on the workload's
+    matrix (one staged copy of H and of Q = I per call, so the timed region is
+    solves only), then the accuracy of the last solve (backward error,
+    orthogonality, and for a prescribed spectrum the distance of every
+    computed eigenvalue to it and back), the run statistics, the kernel-class
     split and the roofline entries of the dominant kernel and of the
     FP64-MFMA update kernel."""
     import numpy as np
     import torch
-    import hqr_inputs as hi
     import paper_2007_03576_amd as hq
     from paper_2007_03576_amd import profiling
-    from scipy.spatial import cKDTree
-    n = 16384
+    spec = WORKLOADS[workload]
+    n = spec["n"]
     dev = torch.device("cuda:0")
-    H, ev = hi.prescribed_hessenberg_device(n, seed=seed, device=dev)
-    Hc = H.t().contiguous()  # row-major storage of H^T = column-major H
-    del H
-    Q = torch.eye(n, dtype=torch.float64, device=dev)
-    A = Hc.clone()
+    H0d, ev = make_input(spec, seed, dev, cache, workload)  # row-major of H^T = column-major H
+    params = {"ns": spec["ns"], "nw": spec["nw"], "streams": streams, "small_shifts": small_shifts}
+    nsteps = warmup + steps
+    Hs = [H0d.clone() for _ in range(nsteps)]
+    Qs = [torch.eye(n, dtype=torch.float64, device=dev) for _ in range(nsteps)]
     wr = torch.empty(n, dtype=torch.float64, device=dev)
     wi = torch.empty_like(wr)
-    params = {"ns": 256, "nw": 1024}
+    infos = []
+    for i in range(warmup):
+        infos.append(hq.schur_colmajor(Hs[i].t(), Qs[i].t(), wr, wi, params=params))
     torch.cuda.synchronize()
     profiling.enable(True)
     profiling.reset()
     t0 = time.perf_counter()
-    info = hq.schur_colmajor(A.t(), Q.t(), wr, wi, params=params)
+    for i in range(warmup, nsteps):
+        infos.append(hq.schur_colmajor(Hs[i].t(), Qs[i].t(), wr, wi, params=params))
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
     prof = profiling.read()
     split = profiling.lds_split()
     profiling.enable(False)
     stats = hq.last_stats()
-    T, Qm, H0 = A.t(), Q.t(), Hc.t()
+    dt = (t1 - t0) / steps
+    assert all(i == 0 for i in infos), infos
+    # accuracy of the last solve (outside the timed region)
+    for i in range(nsteps - 1):
+        Hs[i] = Qs[i] = None
+    torch.cuda.empty_cache()
+    T, Q, H0 = Hs[-1].t(), Qs[-1].t(), H0d.t()
+    u = 2.0 ** -52
     hn = float(torch.linalg.norm(H0))
-    be = float(torch.linalg.norm(Qm.t() @ H0 @ Qm - T)) / hn
-    orth = float(torch.linalg.norm(Qm.t() @ Qm - torch.eye(n, dtype=Qm.dtype, device=dev)))
-    w = wr.cpu().numpy() + 1j * wi.cpu().numpy()
-    P, R = np.c_[w.real, w.imag], np.c_[np.real(ev), np.imag(ev)]
-    dmax = max(cKDTree(R).query(P)[0].max(), cKDTree(P).query(R)[0].max())
-    out = {"workload": "prescribed_hessenberg_n16384 (one solve, ns=256, nw=1024, Q accumulated)",
-           "s": dt, "value": 10.0 * n ** 3 / dt / 1e12, "unit": "TFLOP/s (10n^3 nominal)", "info": info,
-           "accuracy": {"backward_rel": be, "orth": orth, "bound_100nu": 100 * n * 2.0 ** -52,
-                        "eig_dist_max_rel": dmax / hn},
-           "run_stats": stats, "roofline": profiling.roofline(prof, 1),
-           "kernel_times": profiling.summary(prof, 1)}
-    out["kernel_times"]["lds_iteration"]["split"] = split
-    del A, Q, Hc
+    be = float(torch.linalg.norm(Q.t() @ H0 @ Q - T)) / hn
+    orth = float(torch.linalg.norm(Q.t() @ Q - torch.eye(n, dtype=Q.dtype, device=dev)))
+    acc = {"backward_rel": be, "backward_u": be / u, "orth": orth, "bound_100nu": 100 * n * u}
+    if ev is not None:
+        from scipy.spatial import cKDTree
+        w = wr.cpu().numpy() + 1j * wi.cpu().numpy()
+        P, R = np.c_[w.real, w.imag], np.c_[np.real(ev), np.imag(ev)]
+        acc["eig_dist_max_rel"] = max(cKDTree(R).query(P)[0].max(), cKDTree(P).query(R)[0].max()) / hn
+    roof = profiling.roofline(prof, steps)
+    roof["traffic"] = measured_traffic(roof["kernel"], workload)
+    times = profiling.summary(prof, steps)
+    times["lds_iteration"]["split"] = split
+    out = {"workload": workload, "n": n, "ns": spec["ns"], "nw": spec["nw"], "steps": steps, "warmup": warmup,
+           "ms_per_step": dt * 1e3, "value": 10.0 * n ** 3 / dt / 1e12, "unit": "TFLOP/s (10n^3 nominal)",
+           "solves_per_s": 1.0 / dt, "accuracy": acc, "run_stats": stats, "roofline": roof, "kernel_times": times}
+    del Hs, Qs, H0d, T, Q, H0
     torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(spec, seed, target_n):
-    """The oracle on a bounded sample of the same workload (same generator
-    and parameters, order target_n), single thread; returns nominal TFLOP/s."""
-    import oracle
+def host_sample(spec, seed, target_n):
+    """The workload's generator at order target_n, on the host."""
     import hqr_inputs as hi
     if spec["gen"] == "gaussian":
-        H = hi.gaussian_hessenberg(target_n, seed=seed)
-    elif spec["gen"] == "hessrand":
-        H = hi.hessrand(target_n, seed=seed)
-    else:
-        H, _ = hi.prescribed_hessenberg(target_n, seed=seed)
+        return hi.gaussian_hessenberg(target_n, seed=seed)
+    if spec["gen"] == "hessrand":
+        return hi.hessrand(target_n, seed=seed)
+    return hi.prescribed_hessenberg(target_n, seed=seed)[0]
+
+
+def cpu_baseline(spec, H):
+    """The oracle on a bounded sample of the same workload (same generator at
+    a smaller order, the workload's shift count and window when they fit the
+    sample, else the oracle's automatic ones), single thread; returns nominal
+    TFLOP/s."""
+    import oracle
+    n = H.shape[0]
+    ns, nw = (spec["ns"], spec["nw"]) if spec["nw"] <= n // 4 else (0, 0)
     t0 = time.perf_counter()
-    T, Q, w, info, st = oracle.schur(H, want_q=True, ns=spec["ns"], nw=spec["nw"])
+    T, Q, w, info, st = oracle.schur(H, want_q=True, ns=ns, nw=nw)
     dt = time.perf_counter() - t0
     assert info == 0
-    return {"value": 10.0 * target_n ** 3 / dt / 1e12, "unit": "TFLOP/s (10n^3 nominal)", "cores": 1,
+    par = f"ns={ns}, nw={nw}" if ns else "automatic ns and nw (the workload's window exceeds a quarter of the sample)"
+    return {"value": 10.0 * n ** 3 / dt / 1e12, "unit": "TFLOP/s (10n^3 nominal)", "cores": 1,
             "kind": "oracle", "host_cpus": os.cpu_count(),
-            "sample": f"one full solve of the same workload at n={target_n} (same generator, ns={spec['ns']}, "
-                      f"nw={spec['nw']}, Q accumulated): {dt:.2f} s on one thread of a host with "
-                      f"{os.cpu_count()} logical CPUs (the oracle is single-threaded C)"}
+            "sample": f"one full solve of the workload's generator at n={n} ({par}, Q accumulated): {dt:.2f} s "
+                      f"on one thread of a host with {os.cpu_count()} logical CPUs (the oracle is single-threaded C)"}
 
 
-def lapack_context(spec, seed, target_n):
+def lapack_context(H):
     """Context, not the oracle: the host's LAPACK real Schur driver (dgees
     through scipy, OpenBLAS on all its threads) on the same bounded sample as
     cpu_baseline.  dgees also runs the Hessenberg reduction and forms its
@@ -291,18 +326,15 @@ def lapack_context(spec, seed, target_n):
     more than the Schur phase alone."""
     import scipy
     import scipy.linalg as sl
-    import hqr_inputs as hi
     from threadpoolctl import threadpool_info
-    if spec["gen"] != "gaussian":
-        return None
-    H = hi.gaussian_hessenberg(target_n, seed=seed)
+    n = H.shape[0]
     t0 = time.perf_counter()
     sl.schur(H, output="real")
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
-    return {"value": 10.0 * target_n ** 3 / dt / 1e12, "unit": "TFLOP/s (10n^3 nominal)", "threads": threads,
+    return {"value": 10.0 * n ** 3 / dt / 1e12, "unit": "TFLOP/s (10n^3 nominal)", "threads": threads,
             "kind": "LAPACK dgees (scipy %s, OpenBLAS)" % scipy.__version__,
-            "sample": f"one real Schur decomposition of the same generator's matrix at n={target_n}: {dt:.2f} s"}
+            "sample": f"one real Schur decomposition of the same matrix as the oracle's sample (n={n}): {dt:.2f} s"}
 
 
 def main():
@@ -310,17 +342,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gaussian_hessenberg_n4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="prescribed_hessenberg_n16384", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=2020)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batched, differentiation and paper-scale lines")
-    ap.add_argument("--no-paper-scale", action="store_true", help="skip the n = 16384 paper-scale solve")
+                    help="skip the other configuration, the batched and the differentiation lines")
     ap.add_argument("--cpu-n", type=int, default=2048)
     ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--small-shifts", type=int, default=0)
     ap.add_argument("--extra-only", nargs="?", const="all", default=None, choices=["all", "batched", "grad"],
                     help="only the batched and/or differentiation lines (for profiling those kernels)")
+    ap.add_argument("--input-cache", default=None,
+                    help="directory for the generated inputs: read when present, else written")
+    ap.add_argument("--prepare-only", action="store_true",
+                    help="only generate the workload's input into --input-cache")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run 5 plain device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -347,86 +382,52 @@ def main():
         print(json.dumps(out))
         return
 
-    import numpy as np
-    import torch
-    import paper_2007_03576_amd as hq
-    from paper_2007_03576_amd import profiling
-
     spec = WORKLOADS[args.workload]
-    n = spec["n"]
-    dev = torch.device("cuda:0")
-    H0d = make_input(spec, args.seed, dev)  # row-major of H^T = column-major H
-    params = {"ns": spec["ns"], "nw": spec["nw"], "streams": args.streams, "small_shifts": args.small_shifts}
-    nsteps = args.warmup + args.steps
-    # stage one input copy per step so the timed region is solves only
-    Hs = [H0d.clone() for _ in range(nsteps)]
-    eye = torch.eye(n, dtype=torch.float64, device=dev)
-    Qs = [eye.clone() for _ in range(nsteps)]
-    wr = torch.empty(n, dtype=torch.float64, device=dev)
-    wi = torch.empty_like(wr)
-
-    def view(x):  # column-major view of the staged buffer
-        return x.t()
-
-    infos = []
-    for i in range(args.warmup):
-        infos.append(hq.schur_colmajor(view(Hs[i]), view(Qs[i]), wr, wi, params=params))
-    torch.cuda.synchronize()
-    profiling.enable(True)
-    profiling.reset()
-    t0 = time.perf_counter()
-    for i in range(args.warmup, nsteps):
-        infos.append(hq.schur_colmajor(view(Hs[i]), view(Qs[i]), wr, wi, params=params))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = profiling.read()
-    lds_split = profiling.lds_split()
-    profiling.enable(False)
-    stats = hq.last_stats()
-    dt = (t1 - t0) / args.steps
-    assert all(i == 0 for i in infos), infos
-    # accuracy of the last solve (outside the timed region)
-    T = Hs[-1].t()
-    Q = Qs[-1].t()
-    H0 = H0d.t()
-    u = 2.0 ** -52
-    be = float(torch.linalg.norm(Q.t() @ H0 @ Q - T) / torch.linalg.norm(H0))
-    orth = float(torch.linalg.norm(Q.t() @ Q - torch.eye(n, dtype=Q.dtype, device=dev)))
-    nominal = 10.0 * n ** 3
+    if args.prepare_only:
+        import torch
+        if not args.input_cache:
+            print("--prepare-only needs --input-cache", file=sys.stderr)
+            sys.exit(2)
+        make_input(spec, args.seed, torch.device("cuda:0"), args.input_cache, args.workload)
+        print(json.dumps({"prepared": args.workload, "cache": args.input_cache}))
+        return
+    line = solve_line(args.workload, args.seed, args.steps, args.warmup, args.streams, args.small_shifts,
+                      args.input_cache)
     out = {
         "metric": "FP64 TFLOP/s (10n^3 nominal) & Schur solves/sec, batched+grad vs plain, 1 MI355X",
-        "value": nominal / dt / 1e12,
+        "value": line["value"],
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt * 1e3,
+        "ms_per_step": line["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "ns": spec["ns"], "nw": spec["nw"],
+        "config": {"workload": args.workload, "n": spec["n"], "ns": spec["ns"], "nw": spec["nw"],
                    "want_q": True, "seed": args.seed, "streams": args.streams,
                    "small_shifts": args.small_shifts or 2},
-        "solves_per_s": 1.0 / dt,
-        "accuracy": {"backward_rel": be, "backward_u": be / u, "orth": orth, "bound_100nu": 100 * n * u},
-        "run_stats": stats,
+        "solves_per_s": line["solves_per_s"],
+        "accuracy": line["accuracy"],
+        "run_stats": line["run_stats"],
+        "roofline": line["roofline"],
+        "kernel_times": line["kernel_times"],
     }
-    out["roofline"] = profiling.roofline(prof, args.steps)
-    if args.workload == "gaussian_hessenberg_n4096":
-        out["roofline"]["traffic"] = measured_traffic(out["roofline"]["kernel"])
-    out["kernel_times"] = profiling.summary(prof, args.steps)
-    out["kernel_times"]["lds_iteration"]["split"] = lds_split
     if not args.no_extra:
-        out["plain_solves_per_s"] = 1.0 / dt
+        # the other single-matrix configuration, then the batched and differentiated forms
+        other = "gaussian_hessenberg_n4096" if args.workload != "gaussian_hessenberg_n4096" \
+            else "prescribed_hessenberg_n16384"
+        steps2, warm2 = (3, 1) if other == "gaussian_hessenberg_n4096" else (1, 0)
+        out["other_config"] = solve_line(other, args.seed, steps2, warm2, args.streams, args.small_shifts)
+        out["plain_solves_per_s"] = line["solves_per_s"]
         out["batched"] = batched_run(args.seed)
         out["grad"] = grad_run(args.seed)
-        if args.workload != "prescribed_hessenberg_n16384" and not args.no_paper_scale:
-            out["paper_scale"] = paper_scale_run(args.seed)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, args.seed, args.cpu_n)
-        out["lapack_context"] = lapack_context(spec, args.seed, args.cpu_n)
+        H = host_sample(spec, args.seed, args.cpu_n)
+        out["cpu_baseline"] = cpu_baseline(spec, H)
+        out["lapack_context"] = lapack_context(H)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))
