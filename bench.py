@@ -7,7 +7,7 @@ and 4096 conjugate pairs, Haar orthogonal similarity reduced to Hessenberg
 form on the GPU, seed 2020), 256 shifts per sweep and an AED window of 1024,
 Q accumulated from I.  The n = 4096 Gaussian Hessenberg configuration (64
 shifts, window 256), the batched and the differentiated forms are reported
-beside it.  Prints one JSON line (see the design doc for the fields).
+beside it.  Prints one JSON line.
 """
 import argparse
 import json
@@ -370,7 +370,7 @@ def main():
         print(json.dumps({"copy_calib_bytes": nel * 8, "copies": 5}))
         return
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if args.extra_only:

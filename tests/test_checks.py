@@ -1,4 +1,4 @@
-"""The test helpers that judge parity are pinned too: condition numbers from
+"""The test helpers that decide parity are pinned too: condition numbers from
 a quasi-triangular Schur form (used where scipy's eig would be too slow)
 against scipy.linalg.eig's left/right eigenvectors, on normal and non-normal
 matrices with real and complex eigenvalues."""
