@@ -46,3 +46,23 @@ def test_profile_summaries_name_their_commands():
         text = open(os.path.join(prof, f)).read()
         assert "rocprofv3 --kernel-trace --stats" in text, f
         assert "python3 bench.py" in text, f
+
+
+def test_input_cache_round_trip(tmp_path):
+    """--input-cache: the first call generates and writes the input, the
+    second reads back the same matrix and spectrum (host tensors here)."""
+    import numpy as np
+    import torch
+    import bench
+    spec = bench.WORKLOADS["prescribed_hessenberg_n256"]
+    a, ev = bench.make_input(spec, 11, torch.device("cpu"), str(tmp_path), "prescribed_hessenberg_n256")
+    assert (tmp_path / "prescribed_hessenberg_n256_11.npz").exists()
+    b, ev2 = bench.make_input(spec, 11, torch.device("cpu"), str(tmp_path), "prescribed_hessenberg_n256")
+    assert torch.equal(a, b)
+    assert np.array_equal(np.asarray(ev), np.asarray(ev2))
+    c, ev3 = bench.make_input(spec, 11, torch.device("cpu"))
+    assert torch.equal(a, c)
+    # Gaussian inputs carry no spectrum
+    g, gev = bench.make_input(bench.WORKLOADS["gaussian_hessenberg_n4096"], 3, torch.device("cpu"), str(tmp_path), "g")
+    g2, gev2 = bench.make_input(bench.WORKLOADS["gaussian_hessenberg_n4096"], 3, torch.device("cpu"), str(tmp_path), "g")
+    assert gev is None and gev2 is None and torch.equal(g, g2)
