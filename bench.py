@@ -224,6 +224,72 @@ def grad_run(seed):
             "speedup_vs_plain": (512 / (fw + bw)) / plain_rate}
 
 
+def next_rows_run(seed):
+    """The phases around the Schur reduction and the QZ variant, each timed
+    (second of two calls) with its accuracy: the Householder Hessenberg
+    reduction of a dense Gaussian n = 4096 matrix with Q (nominal 10/3 n^3 +
+    4/3 n^3 flops), the eigenvectors of an n = 2048 matrix from its Schur form
+    (residual ||A X - X L|| / (||A|| ||X||)), and the batched QZ variant on
+    2048 random pairs of orders 16..64 (in LDS) and 256 pairs of order 256
+    (global memory), Python packing of the pair lists included."""
+    import numpy as np
+    import torch
+    import hqr_inputs as hi
+    import paper_2007_03576_amd as hq
+    dev = torch.device("cuda:0")
+    out = {}
+    g = torch.Generator(device=dev).manual_seed(seed)
+    n = 4096
+    A = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H, Q = hq.hessenberg(A)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    an = float(torch.linalg.norm(A))
+    be = float(torch.linalg.norm(Q.t() @ A @ Q - H)) / an
+    orth = float(torch.linalg.norm(Q.t() @ Q - torch.eye(n, dtype=Q.dtype, device=dev)))
+    out["hessenberg"] = {"n": n, "s": dt, "tflops_nominal": (14.0 / 3.0) * n ** 3 / dt / 1e12,
+                         "backward_rel": be, "orth": orth, "below_subdiag_zero": bool((torch.tril(H, -2) == 0).all())}
+    del A, H, Q
+    n = 2048
+    Hn = hi.gaussian_hessenberg(n, seed=seed)
+    Hd = torch.from_numpy(np.ascontiguousarray(Hn)).to(dev)
+    T, Q, w, info = hq.schur(Hd)
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X = hq.eigenvectors(T, Q, w)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    Hc = Hd.to(torch.complex128)
+    res = float(torch.linalg.norm(Hc @ X - X * w[None, :])) / (float(torch.linalg.norm(Hd)) *
+                                                            float(torch.linalg.norm(X)))
+    out["eigenvectors"] = {"n": n, "s": dt, "residual_rel": res, "schur_info": info}
+    del Hd, T, Q, X, Hc
+    rng = np.random.default_rng(seed)
+    for name, count, lo, hi_ in (("qz_orders16_64", 2048, 16, 64), ("qz_order256", 256, 256, 256)):
+        sizes = rng.integers(lo, hi_ + 1, size=count)
+        Hs = [torch.from_numpy(np.triu(rng.standard_normal((k, k)), -1)).to(dev) for k in sizes]
+        Ts = [torch.from_numpy(np.triu(rng.standard_normal((k, k)))).to(dev) for k in sizes]
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res_qz = hq.qz_batched(Hs, Ts)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        info_qz = res_qz[-1].cpu().numpy()
+        # backward error of the first pair
+        S0, T0, Q0, Z0 = res_qz[0][0], res_qz[1][0], res_qz[2][0], res_qz[3][0]
+        bh = float(torch.linalg.norm(Q0.t() @ Hs[0] @ Z0 - S0)) / float(torch.linalg.norm(Hs[0]))
+        bt = float(torch.linalg.norm(Q0.t() @ Ts[0] @ Z0 - T0)) / float(torch.linalg.norm(Ts[0]))
+        out[name] = {"pairs": count, "orders": [lo, hi_], "s": dt, "pairs_per_s": count / dt,
+                     "info_max": int(info_qz.max()), "first_pair_backward": [bh, bt]}
+    torch.cuda.empty_cache()
+    return out
+
+
 def solve_line(workload, seed, steps, warmup, streams=2, small_shifts=0, cache=None):
     """`warmup` untimed and `steps` timed hqr_schur calls on the workload's
     matrix (one staged copy of H and of Q = I per call, so the timed region is
@@ -351,7 +417,7 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=2048)
     ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--small-shifts", type=int, default=0)
-    ap.add_argument("--extra-only", nargs="?", const="all", default=None, choices=["all", "batched", "grad"],
+    ap.add_argument("--extra-only", nargs="?", const="all", default=None, choices=["all", "batched", "grad", "next"],
                     help="only the batched and/or differentiation lines (for profiling those kernels)")
     ap.add_argument("--input-cache", default=None,
                     help="directory for the generated inputs: read when present, else written")
@@ -380,6 +446,8 @@ def main():
             out["batched"] = batched_run(args.seed)
         if args.extra_only in ("all", "grad"):
             out["grad"] = grad_run(args.seed)
+        if args.extra_only in ("all", "next"):
+            out["next_rows"] = next_rows_run(args.seed)
         print(json.dumps(out))
         return
 
@@ -425,6 +493,7 @@ def main():
         out["plain_solves_per_s"] = line["solves_per_s"]
         out["batched"] = batched_run(args.seed)
         out["grad"] = grad_run(args.seed)
+        out["next_rows"] = next_rows_run(args.seed)
     if not args.no_cpu_baseline:
         H = host_sample(spec, args.seed, args.cpu_n)
         out["cpu_baseline"] = cpu_baseline(spec, H)
