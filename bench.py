@@ -413,7 +413,7 @@ def main():
     ap.add_argument("--seed", type=int, default=2020)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the other configuration, the batched and the differentiation lines")
+                    help="skip the other configuration and the batched, differentiation and next-row lines")
     ap.add_argument("--cpu-n", type=int, default=2048)
     ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--small-shifts", type=int, default=0)
