@@ -130,16 +130,23 @@ def eigenvectors(T: torch.Tensor, Q: torch.Tensor, w: torch.Tensor, stream=None)
                                 ctypes.c_void_p(X.data_ptr()), max(n, 1), _stream_handle(stream))
     check(rc, "hqr_eigenvectors")
     V = torch.complex(X, torch.zeros_like(X))
+    # columns j, j+1 of a conjugate pair hold Re and Im of the eigenvector of
+    # w[j] (dgeev layout); the pair starts are found on the host, the columns
+    # are unpacked in two vectorized assignments
+    wi_h = wi.cpu().numpy()
+    starts = []
     j = 0
-    wi_h = wi.cpu()
     while j < n:
         if wi_h[j] > 0 and j + 1 < n:
-            re, im = X[:, j], X[:, j + 1]
-            V[:, j] = torch.complex(re, im)
-            V[:, j + 1] = torch.complex(re, -im)
+            starts.append(j)
             j += 2
         else:
             j += 1
+    if starts:
+        p = torch.tensor(starts, dtype=torch.int64, device=X.device)
+        re, im = X[:, p], X[:, p + 1]
+        V[:, p] = torch.complex(re, im)
+        V[:, p + 1] = torch.complex(re, -im)
     return V
 
 
